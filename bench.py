@@ -1,0 +1,232 @@
+"""Benchmark of the direct-summation N-body hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one kick-drift-kick leapfrog step of the whole path: kick and drift
+(FP64), the force evaluation (pack or double-single staging, the FP32 pair
+kernel, the j-split combine, the FP64 epilogue) and the closing kick fused
+with the FP64 energy/momentum diagnostics. Inputs are seeded synthetic
+Plummer spheres (or the cluster ensemble) already resident in HBM.
+
+Prints one JSON line: throughput in G pair-interactions/s (N^2 pair
+evaluations per step, self pairs included, over the measured step time), the
+roofline of the force kernel (20 flops per interaction against the FP32
+vector peak, duration measured with HIP events around every force launch in
+the timed region), the accuracy gate against the FP64 oracle on a target
+subsample, and the FP64 oracle's own rate on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+FLOPS_PER_INTERACTION = 20        # the conventional count for one softened pair
+DEFAULT_VARIANT = {"plummer_1k": "plain", "plummer_64k": "plain", "plummer_256k": "comp",
+                   "kroupa_1m": "comp", "ensemble_512": "comp"}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="plummer_64k",
+                    choices=sorted(DEFAULT_VARIANT))
+    ap.add_argument("--variant", default=None, choices=["plain", "comp"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(pos, mass, eps, budget_s):
+    """Time the FP64 C oracle on a strided target sample against all sources,
+    sized to about ``budget_s`` seconds of host time. Returns the rate, the
+    sample description and the oracle's values on the sample (used for the
+    accuracy gate)."""
+    from oracle import cpu as ocpu
+    from oracle import oracle as orc
+
+    ocpu.build(force=False)
+    n = len(mass)
+    threads = ocpu.max_threads()
+    probe = orc.subsample_targets(n, min(n, 64))
+    t0 = time.perf_counter()
+    ocpu.accel_pot(pos, mass, eps, targets=probe)
+    dt = max(time.perf_counter() - t0, 1e-6)
+    rate = len(probe) * n / dt
+    nt = int(min(n, max(256, budget_s * rate / n)))
+    nt = min(nt, 4096) if n > 4096 else nt
+    tgt = orc.subsample_targets(n, nt)
+    t0 = time.perf_counter()
+    ref_a, ref_p = ocpu.accel_pot(pos, mass, eps, targets=tgt)
+    el = time.perf_counter() - t0
+    pairs = len(tgt) * n
+    return {
+        "value": pairs / el / 1e9,
+        "unit": "G pair-interactions/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{len(tgt)} strided targets x {n} sources ({pairs:.3e} FP64 pairs, {el:.2f} s, "
+                  f"C/OpenMP, {threads} threads)",
+    }, tgt, ref_a, ref_p
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 "
+                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2509_19294_amd import ics, nbody
+
+    nbody.load()
+    dev = torch.device("cuda:0")
+    name = args.workload
+    variant = args.variant or DEFAULT_VARIANT[name]
+    plan = None
+    if name == "ensemble_512":
+        ens, spec = ics.workload(name)
+        pos, vel, mass = ens.pos, ens.vel, ens.mass
+        eps = 0.0
+        plan = nbody.Plan(ens.offsets, ens.eps, variant)
+        pairs_per_eval = plan.pairs
+        n = len(mass)
+    else:
+        pos, vel, mass, spec = ics.workload(name)
+        eps = spec["eps"]
+        n = len(mass)
+        pairs_per_eval = float(n) * float(n)
+    dt = spec["dt"]
+
+    tp = torch.from_numpy(pos).to(dev)
+    tv = torch.from_numpy(vel).to(dev)
+    tm = torch.from_numpy(mass).to(dev)
+    pot = torch.empty_like(tm)
+    if plan is not None:
+        acc, _ = plan.accel(tp, tm, 1.0, pot=pot)
+    else:
+        acc, _ = nbody.accel(tp, tm, eps, 1.0, variant, pot=pot)
+    torch.cuda.synchronize()
+    acc0 = acc.cpu().numpy()
+    pot0 = pot.cpu().numpy()
+
+    diag = torch.empty((1, nbody.DIAG_LEN), dtype=torch.float64, device=dev)
+
+    def one_step():
+        nbody.step(tp, tv, acc, tm, eps, 1.0, dt, 1, variant, plan=plan, diag=diag, pot=pot)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream(dev)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    nbody.timing_enable(plan is None)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    start.record(stream)
+    for _ in range(args.steps):
+        one_step()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms_total = start.elapsed_time(stop)
+    launches, kernel_ms = nbody.timing_read()
+    nbody.timing_enable(False)
+
+    if plan is not None:
+        # The batched force kernel runs inside the graph replay: time it
+        # eagerly, bracketed the same way, on the same stream and inputs.
+        nbody.timing_enable(True)
+        for _ in range(args.steps):
+            plan.accel(tp, tm, 1.0, acc=acc, pot=pot)
+        torch.cuda.synchronize()
+        launches, kernel_ms = nbody.timing_read()
+        nbody.timing_enable(False)
+
+    ms_per_step = ms_total / args.steps
+    value = pairs_per_eval / (ms_per_step * 1e-3) / 1e9
+    kernel_avg_ms = kernel_ms / max(launches, 1)
+    achieved = FLOPS_PER_INTERACTION * pairs_per_eval / (kernel_avg_ms * 1e-3) / 1e12
+
+    out = {
+        "metric": "G pair-interactions/s and % FP32 VALU peak at rel-RMS accel err <=1e-5 vs FP64",
+        "value": round(value, 2),
+        "unit": "G pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{name}: " + (
+                f"{len(plan.eps)} Plummer clusters, N_total={n}" if plan is not None
+                else f"Plummer sphere N={n}" + (" Kroupa masses" if name == "kroupa_1m" else "")
+                + f", eps={eps}") + f", dt={dt}, one KDK step with diagnostics",
+            "variant": variant,
+            "n": n,
+            "pairs_per_step": pairs_per_eval,
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": round(achieved, 2),
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+            "traffic": None,
+            "kernel_avg_ms": round(kernel_avg_ms, 4),
+            "kernel_launches": launches,
+            "flops_per_interaction": FLOPS_PER_INTERACTION,
+        },
+    }
+
+    if not args.no_cpu_baseline:
+        from oracle import oracle as orc
+
+        if plan is not None:
+            # one mid-sized cluster's targets against its own sources
+            k = int(np.argsort(ens.sizes)[len(ens.sizes) // 2])
+            s, e = int(ens.offsets[k]), int(ens.offsets[k + 1])
+            cb, tgt, ref_a, ref_p = cpu_baseline(pos[s:e], mass[s:e], float(ens.eps[k]), args.cpu_seconds)
+            a_s, p_s = acc0[s:e][tgt], pot0[s:e][tgt]
+        else:
+            cb, tgt, ref_a, ref_p = cpu_baseline(pos, mass, eps, args.cpu_seconds)
+            a_s, p_s = acc0[tgt], pot0[tgt]
+        out["cpu_baseline"] = cb
+        acc_err = orc.rel_rms(a_s, ref_a)
+        out["accuracy"] = {
+            "acc_rel_rms": float(f"{acc_err:.3e}"),
+            "acc_max_rel": float(f"{orc.max_rel(a_s, ref_a):.3e}"),
+            "pot_rel_rms": float(f"{orc.rel_rms(p_s, ref_p):.3e}"),
+            "targets": int(len(tgt)),
+            "gate_rel_rms_1e-5": bool(acc_err <= 1e-5),
+        }
+        if acc_err > 1e-5:
+            out["value"] = None
+            out["note"] = "accuracy gate failed: throughput not reported"
+    print(json.dumps(out), flush=True)
+    if plan is not None:
+        plan.close()
+
+
+if __name__ == "__main__":
+    main()

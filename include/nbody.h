@@ -1,0 +1,191 @@
+/*
+ * nbody.h - C ABI of libnbody.so: direct-summation gravitational N-body on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * What is computed. The force equation of Section 3 of Almerol et al.,
+ * "Accelerating Gravitational N-Body Simulations Using the RISC-V-Based
+ * Tenstorrent Wormhole" (SC'25 Workshops): the force on particle i is the
+ * sum over every other particle j != i of G m_i m_j (r_j - r_i) / r_ij^3.
+ * This library returns it per unit target mass, with Plummer softening eps:
+ *
+ *     a_i   =  G sum_{j != i} m_j (x_j - x_i) / (|x_j - x_i|^2 + eps^2)^(3/2)
+ *     phi_i = -G sum_{j != i} m_j / (|x_j - x_i|^2 + eps^2)^(1/2)
+ *
+ * eps = 0 is the paper's unsoftened sum exactly. The pair arithmetic runs in
+ * FP32 on the GPU, as the paper's device force does (Section 3,
+ * mixed-precision paragraph); positions, velocities, the integrator and all
+ * outputs are FP64.
+ *
+ * Conventions for every call below.
+ *  - Array pointers are DEVICE pointers unless the name ends in _host. The
+ *    caller owns every buffer; the calls in this header never allocate device
+ *    memory, except nbody_plan_create, which owns what it allocates until
+ *    nbody_plan_destroy.
+ *  - Arrays are C-contiguous: pos, vel, acc are [n][3] float64 (x, y, z of a
+ *    particle adjacent); mass and pot are [n] float64.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued asynchronously on it; the call returns without
+ *    synchronising. Device faults surface at the caller's next
+ *    synchronisation, as for any HIP launch.
+ *  - Validation is synchronous and host-side, before any launch. On any
+ *    non-OK status nothing has been enqueued and outputs are untouched;
+ *    nbody_last_error() then describes the problem.
+ *  - Input and output arrays must not overlap, except where stated.
+ *  - Results are deterministic: the same inputs and tuning give bitwise the
+ *    same outputs on every run (no floating-point atomics).
+ *  - Calls from several host threads are safe if they use distinct buffers;
+ *    calls that share a workspace or a plan must be ordered by the caller.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nbody_status;
+#define NBODY_OK 0
+#define NBODY_EINVAL 1      /* a null pointer, size or scalar out of range   */
+#define NBODY_ENOTSUP 2     /* a variant or size this build does not handle  */
+#define NBODY_EWORKSPACE 3  /* workspace missing or smaller than required    */
+#define NBODY_EHIP 4        /* the HIP runtime returned an error             */
+
+/* Pair-kernel forms. */
+#define NBODY_FP32_PLAIN 0  /* FP32 coordinates and sums (two-level: per tile, then running) */
+#define NBODY_FP32_COMP 1   /* FP32 pair arithmetic on double-single (hi, lo) coordinates
+                               relative to a per-block FP64 frame, compensated (TwoSum)
+                               accumulation, FP64 epilogue */
+
+/* One diagnostics row (float64), written after every step by nbody_step. */
+#define NBODY_DIAG_LEN 16
+#define NBODY_DIAG_K 0        /* kinetic energy 1/2 sum m |v|^2                  */
+#define NBODY_DIAG_W 1        /* potential energy 1/2 sum m phi                  */
+#define NBODY_DIAG_E 2        /* K + W                                           */
+#define NBODY_DIAG_P 3        /* [3] total momentum sum m v                      */
+#define NBODY_DIAG_L 6        /* [3] total angular momentum sum m x cross v      */
+#define NBODY_DIAG_COM 9      /* [3] centre of mass sum m x / sum m              */
+#define NBODY_DIAG_M 12       /* total mass                                      */
+#define NBODY_DIAG_NONFINITE 13 /* number of non-finite entries in pos and vel   */
+#define NBODY_DIAG_STEP 14    /* step index within the call, starting at 1       */
+
+/* Opaque batched plan: many independent clusters, their work list and tuning. */
+typedef struct nbody_plan nbody_plan;
+
+/* Bytes of device workspace the calls below need for a system of n_total
+ * particles in n_clusters clusters (1 for a single system) with `variant`.
+ * Pure host arithmetic; returns 0 for invalid arguments (n_total < 0,
+ * n_clusters < 1, unknown variant). */
+size_t nbody_workspace_bytes(int64_t n_total, int32_t n_clusters, int32_t variant);
+
+/* Text of the last non-OK status on the calling thread ("" if none). The
+ * pointer stays valid until the next call on that thread. */
+const char *nbody_last_error(void);
+
+/* Library version string. */
+const char *nbody_version(void);
+
+/* Accelerations (and potentials) of a single system (the force equation of
+ * Section 3, softened by eps).
+ *   pos   [n][3] f64 in; mass [n] f64 in (any finite values >= 0).
+ *   n >= 0 (n = 0 is a no-op; n = 1 gives acc = pot = 0).
+ *   eps >= 0 and finite; eps = 0 excludes j == i and any pair at zero
+ *   separation (coincident distinct particles at eps = 0 are undefined).
+ *   G finite.
+ *   variant NBODY_FP32_PLAIN or NBODY_FP32_COMP.
+ *   acc [n][3] f64 out; pot [n] f64 out or NULL.
+ *   ws: device workspace of ws_bytes >= nbody_workspace_bytes(n, 1, variant).
+ * Errors: EINVAL (null pos/mass/acc with n > 0, n < 0, bad eps/G, overlap of
+ * acc with pos), ENOTSUP (unknown variant), EWORKSPACE, EHIP. */
+nbody_status nbody_accel(const double *pos, const double *mass, int64_t n,
+                         double eps, double G, int32_t variant,
+                         double *acc, double *pot,
+                         void *ws, size_t ws_bytes, void *stream);
+
+/* n_steps kick-drift-kick leapfrog steps (all FP64 on the GPU, forces by the
+ * chosen variant). Per step: v += dt/2 a; x += dt v; a = A(x); v += dt/2 a.
+ *   pos, vel [n][3] f64 in/out; acc [n][3] f64 in/out: on entry it must hold
+ *   A(pos) (call nbody_accel once first), on return A(pos_final).
+ *   pot [n] f64 out (potentials at the final positions) or NULL.
+ *   mass [n] f64 in. eps, G, variant as for nbody_accel; dt finite;
+ *   n_steps >= 0.
+ *   plan: NULL for a single system; otherwise a plan from nbody_plan_create
+ *   whose clusters cover exactly n particles, in which case eps is ignored
+ *   (each cluster uses its own) and variant must match the plan's.
+ *   diag [n_steps][NBODY_DIAG_LEN] f64 out or NULL: one row after each step.
+ *   ws as for nbody_accel (nbody_workspace_bytes(n, K, variant)).
+ * With a plan, each step is one replay of a HIP graph the plan captures on
+ * first use for this set of pointers and scalars. */
+nbody_status nbody_step(double *pos, double *vel, double *acc, double *pot,
+                        const double *mass, int64_t n, double eps, double G,
+                        double dt, int32_t n_steps, int32_t variant,
+                        nbody_plan *plan, double *diag,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* Build a plan for K independent clusters. Cluster k owns particles
+ * [offsets_host[k], offsets_host[k+1]) and is softened by eps_host[k];
+ * clusters exert no force on one another.
+ *   offsets_host [K+1] int64 host, offsets_host[0] = 0, non-decreasing.
+ *   eps_host [K] f64 host, each >= 0 and finite.
+ *   variant as above. tune_path: a tuning file written by the autotuner, or
+ *   NULL for built-in defaults (the NBODY_TUNE environment variable, if set,
+ *   names a file used when tune_path is NULL).
+ * Allocates device memory for the work list and the graph. Returns NULL on
+ * error (see nbody_last_error). */
+nbody_plan *nbody_plan_create(const int64_t *offsets_host, int32_t K,
+                              const double *eps_host, int32_t variant,
+                              const char *tune_path);
+
+/* Free a plan (NULL is a no-op). The caller must ensure no enqueued work
+ * still uses it. */
+void nbody_plan_destroy(nbody_plan *plan);
+
+/* Accelerations and potentials of every cluster of `plan`, each from its own
+ * members only, in one persistent-kernel launch.
+ *   pos [n_total][3], mass [n_total] in; acc [n_total][3] out; pot [n_total]
+ *   out or NULL; n_total = offsets_host[K]. G finite.
+ *   ws: ws_bytes >= nbody_workspace_bytes(n_total, K, variant). */
+nbody_status nbody_accel_batched(const double *pos, const double *mass,
+                                 nbody_plan *plan, double G,
+                                 double *acc, double *pot,
+                                 void *ws, size_t ws_bytes, void *stream);
+
+/* Number of particles and clusters a plan covers, and its variant. */
+int64_t nbody_plan_total(const nbody_plan *plan);
+int32_t nbody_plan_clusters(const nbody_plan *plan);
+int32_t nbody_plan_variant(const nbody_plan *plan);
+/* Number of (cluster, i-block) work items and sum of their pair counts. */
+int64_t nbody_plan_items(const nbody_plan *plan);
+double nbody_plan_pairs(const nbody_plan *plan);
+
+/* Tuning. A configuration is (block threads, i per thread, lanes per i,
+ * waves per i-group, j-tile, grid j-split). nbody_tune_set forces one for a
+ * variant and size class until reset (cfg = -1 restores the table entry);
+ * nbody_tune_count and nbody_tune_describe enumerate the compiled set. Used
+ * by the autotuner; size_class = floor(log2(n)). */
+int32_t nbody_tune_count(int32_t variant);
+nbody_status nbody_tune_describe(int32_t variant, int32_t cfg, int32_t *out6);
+nbody_status nbody_tune_set(int32_t variant, int32_t size_class, int32_t cfg);
+int32_t nbody_tune_get(int32_t variant, int64_t n);
+nbody_status nbody_tune_load(const char *path);
+/* Restore the built-in tuning table (then NBODY_TUNE, if set) and clear
+ * every forced configuration. */
+nbody_status nbody_tune_reset(void);
+
+/* Kernel timing, for measurement. While enabled (on != 0), every
+ * force-kernel launch made outside graph capture by nbody_accel, nbody_step
+ * and nbody_accel_batched is bracketed by HIP events recorded on the stream
+ * it runs on (the bracket covers the pair kernel and, with a grid j-split, its
+ * combine kernel). nbody_timing_read waits for those events, returns the
+ * number of bracketed launches and their summed duration in milliseconds, and
+ * clears the record. Enabling or disabling also clears it. Not thread-safe:
+ * meant for one measuring thread. */
+nbody_status nbody_timing_enable(int32_t on);
+nbody_status nbody_timing_read(int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBODY_H */

@@ -1,0 +1,653 @@
+// C ABI of libnbody.so (declared in include/nbody.h): host-side validation,
+// workspace layout, tuning lookup, kernel dispatch, batched plans and their
+// HIP graphs. Every device-side step runs in the kernels of kernels.hip.
+#include "nbody.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "nbody_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+nbody_status fail(nbody_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+nbody_status hip_fail(hipError_t e, const char *what) {
+  return fail(NBODY_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool valid_variant(int32_t v) { return v == NBODY_FP32_PLAIN || v == NBODY_FP32_COMP; }
+
+size_t align_up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// Workspace layout (offsets in bytes from the base, each 256-byte aligned).
+struct WsLayout {
+  size_t packed, part, pot, diag, ctr, total;
+};
+
+WsLayout ws_layout(int64_t n, int32_t variant) {
+  WsLayout L{};
+  const size_t un = static_cast<size_t>(n);
+  const size_t jw = variant == NBODY_FP32_COMP ? 2 : 1;
+  size_t off = 0;
+  L.packed = off;
+  off += align_up(un * sizeof(float4));
+  L.part = off;
+  off += align_up(static_cast<size_t>(nb::kMaxSplit) * un * jw * sizeof(float4));
+  L.pot = off;
+  off += align_up(un * sizeof(double));
+  L.diag = off;
+  off += align_up(static_cast<size_t>(nb::kDiagBlocks) * nb::kDiagLen * sizeof(double));
+  L.ctr = off;
+  off += 256;
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+T *at(void *ws, size_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb_) {
+  if (!a || !b || na == 0 || nb_ == 0) return false;
+  const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+  return pa < pb + nb_ && pb < pa + na;
+}
+
+// ---------------------------------------------------------------------------
+// Tuning: per variant and size class (floor(log2(n))), a single-system
+// configuration index and grid j-split, and a batched mode.
+
+constexpr int kClasses = 48;
+
+struct SingleTune {
+  int cfg;
+  int split;
+};
+
+std::mutex g_tune_mu;
+SingleTune g_single[2][kClasses];
+int g_batched[2][kClasses];
+bool g_tune_init = false;
+int g_forced[2][kClasses];  // -1 = none
+
+int size_class(int64_t n) {
+  int c = 0;
+  while (c + 1 < kClasses && (int64_t{1} << (c + 1)) <= n) ++c;
+  return c;
+}
+
+void tune_defaults() {
+  for (int v = 0; v < 2; ++v) {
+    for (int c = 0; c < kClasses; ++c) {
+      // Default: two i per thread, 256-wide tiles, enough grid j-split to put
+      // about 1024 blocks on the device for mid-size systems.
+      g_single[v][c] = SingleTune{1, 1};
+      const int64_t n = int64_t{1} << c;
+      const int64_t blocks = (n + 511) / 512;
+      int split = 1;
+      while (split < nb::kMaxSplit && blocks * split < 1024 && n / (split * 2) >= 2048) split *= 2;
+      g_single[v][c].split = split;
+      g_batched[v][c] = c < 10 ? 0 : (c < 11 ? 1 : 2);
+      g_forced[v][c] = -1;
+    }
+  }
+}
+
+nbody_status tune_load_locked(const char *path) {
+  FILE *f = std::fopen(path, "r");
+  if (!f) return fail(NBODY_EINVAL, "cannot open tuning file '%s'", path);
+  char line[256];
+  int lineno = 0;
+  while (std::fgets(line, sizeof(line), f)) {
+    ++lineno;
+    char kind[32];
+    int v, c, a, b = 1;
+    if (line[0] == '#' || line[0] == '\n') continue;
+    const int got = std::sscanf(line, "%31s %d %d %d %d", kind, &v, &c, &a, &b);
+    if (got < 4 || v < 0 || v > 1 || c < 0 || c >= kClasses) {
+      std::fclose(f);
+      return fail(NBODY_EINVAL, "tuning file '%s' line %d malformed", path, lineno);
+    }
+    if (std::strcmp(kind, "single") == 0) {
+      if (a < 0 || a >= nb::single_cfg_count() || b < 1 || b > nb::kMaxSplit) {
+        std::fclose(f);
+        return fail(NBODY_EINVAL, "tuning file '%s' line %d: bad single entry", path, lineno);
+      }
+      g_single[v][c] = SingleTune{a, b};
+    } else if (std::strcmp(kind, "batched") == 0) {
+      if (a < 0 || a >= nb::batched_mode_count()) {
+        std::fclose(f);
+        return fail(NBODY_EINVAL, "tuning file '%s' line %d: bad batched entry", path, lineno);
+      }
+      g_batched[v][c] = a;
+    } else {
+      std::fclose(f);
+      return fail(NBODY_EINVAL, "tuning file '%s' line %d: unknown kind", path, lineno);
+    }
+  }
+  std::fclose(f);
+  return NBODY_OK;
+}
+
+void tune_init_locked() {
+  if (g_tune_init) return;
+  tune_defaults();
+  g_tune_init = true;
+  const char *env = std::getenv("NBODY_TUNE");
+  if (env && *env) tune_load_locked(env);  // a bad file leaves the defaults
+}
+
+SingleTune single_tune(int32_t variant, int64_t n) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_init_locked();
+  const int c = size_class(n);
+  SingleTune t = g_single[variant][c];
+  if (g_forced[variant][c] >= 0) {
+    const int f = g_forced[variant][c];
+    t = SingleTune{f % 1000, f / 1000 > 0 ? f / 1000 : 1};
+  }
+  return t;
+}
+
+int batched_tune(int32_t variant, int64_t nk) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_init_locked();
+  return g_batched[variant][size_class(nk)];
+}
+
+// ---------------------------------------------------------------------------
+// Optional event brackets around force-kernel launches (measurement only).
+
+struct Timing {
+  bool on = false;
+  std::vector<hipEvent_t> pool;  // pairs: start at 2k, stop at 2k + 1
+  size_t used = 0;               // events recorded since the last read
+};
+Timing g_timing;
+
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
+  return cs != hipStreamCaptureStatusNone;
+}
+
+hipEvent_t timing_event() {
+  if (g_timing.used == g_timing.pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_timing.pool.push_back(e);
+  }
+  return g_timing.pool[g_timing.used++];
+}
+
+// Records the start event; returns the stop event to record after the launch
+// (nullptr when timing is off or the stream is being captured).
+hipEvent_t timing_begin(hipStream_t st) {
+  if (!g_timing.on || capturing(st)) return nullptr;
+  hipEvent_t a = timing_event();
+  if (!a) return nullptr;
+  hipEvent_t b = timing_event();
+  if (!b) {
+    --g_timing.used;
+    return nullptr;
+  }
+  if (hipEventRecord(a, st) != hipSuccess) {
+    g_timing.used -= 2;
+    return nullptr;
+  }
+  return b;
+}
+
+void timing_end(hipEvent_t stop, hipStream_t st) {
+  if (stop) (void)hipEventRecord(stop, st);
+}
+
+// ---------------------------------------------------------------------------
+// Shared pieces of accel / step.
+
+nbody_status check_scalars(double eps, double G) {
+  if (!std::isfinite(eps) || eps < 0.0) return fail(NBODY_EINVAL, "eps must be finite and >= 0 (got %g)", eps);
+  if (!std::isfinite(G)) return fail(NBODY_EINVAL, "G must be finite");
+  return NBODY_OK;
+}
+
+nbody_status check_ws(void *ws, size_t ws_bytes, int64_t n, int32_t variant) {
+  const size_t need = ws_layout(n, variant).total;
+  if (!ws) return fail(NBODY_EWORKSPACE, "workspace is NULL (need %zu bytes)", need);
+  if (ws_bytes < need) return fail(NBODY_EWORKSPACE, "workspace of %zu bytes < %zu required", ws_bytes, need);
+  return NBODY_OK;
+}
+
+hipError_t enqueue_accel(const double *pos, const double *mass, int64_t n, double eps, double G,
+                         int32_t variant, double *acc, double *pot, void *ws, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const WsLayout L = ws_layout(n, variant);
+  const SingleTune t = single_tune(variant, n);
+  const bool comp = variant == NBODY_FP32_COMP;
+  float4 *packed = at<float4>(ws, L.packed);
+  if (!comp) {
+    const hipError_t e = nb::launch_pack(pos, mass, n, packed, st);
+    if (e != hipSuccess) return e;
+  }
+  hipEvent_t stop = timing_begin(st);
+  const hipError_t e = nb::launch_pair_single(t.cfg, comp, pos, mass, packed, n, eps, G, t.split,
+                                              acc, pot, at<float4>(ws, L.part), st);
+  timing_end(stop, st);
+  return e;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batched plan.
+
+struct nbody_plan {
+  int32_t K = 0;
+  int32_t variant = 0;
+  int64_t n_total = 0;
+  std::vector<int64_t> offsets;
+  std::vector<double> eps;
+  int32_t n_items = 0;
+  double pairs = 0.0;
+  nb::Item *d_items = nullptr;
+  double *d_eps = nullptr;
+  int grid = 0;
+  int device = 0;
+  hipStream_t capture = nullptr;
+  // Cached graph of one KDK step and the arguments it was captured with.
+  hipGraphExec_t exec = nullptr;
+  const void *key[9] = {};
+  double key_g = 0, key_dt = 0;
+};
+
+namespace {
+
+hipError_t enqueue_batched(const double *pos, const double *mass, nbody_plan *p, double G,
+                           double *acc, double *pot, void *ws, hipStream_t st) {
+  const WsLayout L = ws_layout(p->n_total, p->variant);
+  hipEvent_t stop = timing_begin(st);
+  const hipError_t e = nb::launch_pair_batched(
+      p->variant == NBODY_FP32_COMP, pos, mass, at<float4>(ws, L.packed), p->n_total, p->d_items,
+      p->n_items, p->d_eps, G, p->grid, at<int>(ws, L.ctr) + 4, acc, pot, st);
+  timing_end(stop, st);
+  return e;
+}
+
+// One KDK step: kick-drift, forces, kick (+ diagnostics row).
+hipError_t enqueue_step(double *pos, double *vel, double *acc, double *pot, const double *mass,
+                        int64_t n, double eps, double G, double dt, int32_t variant,
+                        nbody_plan *plan, double *diag, void *ws, hipStream_t st) {
+  const WsLayout L = ws_layout(n, variant);
+  const double h = 0.5 * dt;
+  hipError_t e = nb::launch_kick_drift(pos, vel, acc, n, h, dt, st);
+  if (e != hipSuccess) return e;
+  double *potw = pot ? pot : (diag ? at<double>(ws, L.pot) : nullptr);
+  if (plan)
+    e = enqueue_batched(pos, mass, plan, G, acc, potw, ws, st);
+  else
+    e = enqueue_accel(pos, mass, n, eps, G, variant, acc, potw, ws, st);
+  if (e != hipSuccess) return e;
+  if (diag) {
+    e = nb::launch_kick_diag(pos, vel, acc, potw, mass, n, h, at<double>(ws, L.diag), st);
+    if (e != hipSuccess) return e;
+    return nb::launch_diag_final(at<double>(ws, L.diag), diag, at<int>(ws, L.ctr), st);
+  }
+  return nb::launch_kick(vel, acc, n, h, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nbody_last_error(void) { return g_err.c_str(); }
+
+const char *nbody_version(void) { return "nbody-mi355x 0.1 (gfx950)"; }
+
+size_t nbody_workspace_bytes(int64_t n_total, int32_t n_clusters, int32_t variant) {
+  if (n_total < 0 || n_clusters < 1 || !valid_variant(variant)) return 0;
+  return ws_layout(n_total, variant).total;
+}
+
+nbody_status nbody_accel(const double *pos, const double *mass, int64_t n, double eps, double G,
+                         int32_t variant, double *acc, double *pot, void *ws, size_t ws_bytes,
+                         void *stream) {
+  g_err.clear();
+  if (n < 0) return fail(NBODY_EINVAL, "n must be >= 0 (got %lld)", static_cast<long long>(n));
+  if (!valid_variant(variant)) return fail(NBODY_ENOTSUP, "unknown variant %d", variant);
+  nbody_status st = check_scalars(eps, G);
+  if (st != NBODY_OK) return st;
+  if (n == 0) return NBODY_OK;
+  if (!pos || !mass || !acc) return fail(NBODY_EINVAL, "pos, mass and acc must be non-NULL");
+  const size_t b3 = static_cast<size_t>(n) * 3 * sizeof(double), b1 = static_cast<size_t>(n) * sizeof(double);
+  if (overlap(acc, b3, pos, b3) || overlap(acc, b3, mass, b1) || overlap(pot, b1, pos, b3) ||
+      overlap(pot, b1, mass, b1) || overlap(pot, b1, acc, b3))
+    return fail(NBODY_EINVAL, "output arrays overlap inputs or each other");
+  st = check_ws(ws, ws_bytes, n, variant);
+  if (st != NBODY_OK) return st;
+  const hipError_t e = enqueue_accel(pos, mass, n, eps, G, variant, acc, pot, ws,
+                                     static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "nbody_accel launch");
+  return NBODY_OK;
+}
+
+nbody_plan *nbody_plan_create(const int64_t *offsets_host, int32_t K, const double *eps_host,
+                              int32_t variant, const char *tune_path) {
+  g_err.clear();
+  if (!offsets_host || !eps_host) {
+    fail(NBODY_EINVAL, "offsets and eps must be non-NULL");
+    return nullptr;
+  }
+  if (K < 1) {
+    fail(NBODY_EINVAL, "K must be >= 1 (got %d)", K);
+    return nullptr;
+  }
+  if (!valid_variant(variant)) {
+    fail(NBODY_ENOTSUP, "unknown variant %d", variant);
+    return nullptr;
+  }
+  if (offsets_host[0] != 0) {
+    fail(NBODY_EINVAL, "offsets[0] must be 0");
+    return nullptr;
+  }
+  for (int32_t k = 0; k < K; ++k) {
+    if (offsets_host[k + 1] < offsets_host[k]) {
+      fail(NBODY_EINVAL, "offsets must be non-decreasing (at %d)", k);
+      return nullptr;
+    }
+    if (!std::isfinite(eps_host[k]) || eps_host[k] < 0.0) {
+      fail(NBODY_EINVAL, "eps[%d] must be finite and >= 0", k);
+      return nullptr;
+    }
+  }
+  if (offsets_host[K] >= (int64_t{1} << 31)) {
+    fail(NBODY_ENOTSUP, "batched plans hold fewer than 2^31 particles");
+    return nullptr;
+  }
+  if (tune_path) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_init_locked();
+    if (tune_load_locked(tune_path) != NBODY_OK) return nullptr;
+  }
+
+  nbody_plan *p = new nbody_plan();
+  p->K = K;
+  p->variant = variant;
+  p->offsets.assign(offsets_host, offsets_host + K + 1);
+  p->eps.assign(eps_host, eps_host + K);
+  p->n_total = offsets_host[K];
+
+  // Work items: every cluster cut into i-blocks of its mode's width; then
+  // heaviest first (longest-processing-time order), ties by position.
+  std::vector<nb::Item> items;
+  for (int32_t k = 0; k < K; ++k) {
+    const int64_t s = p->offsets[k], e = p->offsets[k + 1], nk = e - s;
+    if (nk == 0) continue;
+    const int mode = batched_tune(variant, nk);
+    const int ib = nb::cfg_iblock(nb::batched_mode(mode));
+    for (int64_t i = s; i < e; i += ib) {
+      nb::Item it{};
+      it.i0 = static_cast<int32_t>(i);
+      it.i1 = static_cast<int32_t>(std::min<int64_t>(i + ib, e));
+      it.j0 = static_cast<int32_t>(s);
+      it.j1 = static_cast<int32_t>(e);
+      it.cluster = k;
+      it.mode = mode;
+      items.push_back(it);
+      p->pairs += static_cast<double>(it.i1 - it.i0) * static_cast<double>(nk);
+    }
+  }
+  std::stable_sort(items.begin(), items.end(), [](const nb::Item &a, const nb::Item &b) {
+    const int64_t ca = int64_t{a.i1 - a.i0} * (a.j1 - a.j0);
+    const int64_t cb = int64_t{b.i1 - b.i0} * (b.j1 - b.j0);
+    return ca > cb;
+  });
+  p->n_items = static_cast<int32_t>(items.size());
+
+  hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess && !items.empty()) e = hipMalloc(&p->d_items, items.size() * sizeof(nb::Item));
+  if (e == hipSuccess && !items.empty())
+    e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(nb::Item), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&p->d_eps, static_cast<size_t>(K) * sizeof(double));
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_eps, p->eps.data(), static_cast<size_t>(K) * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
+  if (e == hipSuccess) {
+    p->grid = nb::batched_grid(variant == NBODY_FP32_COMP);
+    if (p->grid <= 0) e = hipErrorInvalidDeviceFunction;
+    if (p->grid > p->n_items && p->n_items > 0) p->grid = p->n_items;
+    if (p->grid < 1) p->grid = 1;
+  }
+  if (e != hipSuccess) {
+    hip_fail(e, "nbody_plan_create");
+    nbody_plan_destroy(p);
+    return nullptr;
+  }
+  return p;
+}
+
+void nbody_plan_destroy(nbody_plan *p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->capture) (void)hipStreamDestroy(p->capture);
+  if (p->d_items) (void)hipFree(p->d_items);
+  if (p->d_eps) (void)hipFree(p->d_eps);
+  delete p;
+}
+
+int64_t nbody_plan_total(const nbody_plan *p) { return p ? p->n_total : -1; }
+int32_t nbody_plan_clusters(const nbody_plan *p) { return p ? p->K : -1; }
+int32_t nbody_plan_variant(const nbody_plan *p) { return p ? p->variant : -1; }
+int64_t nbody_plan_items(const nbody_plan *p) { return p ? p->n_items : -1; }
+double nbody_plan_pairs(const nbody_plan *p) { return p ? p->pairs : -1.0; }
+
+nbody_status nbody_accel_batched(const double *pos, const double *mass, nbody_plan *plan, double G,
+                                 double *acc, double *pot, void *ws, size_t ws_bytes,
+                                 void *stream) {
+  g_err.clear();
+  if (!plan) return fail(NBODY_EINVAL, "plan is NULL");
+  if (!std::isfinite(G)) return fail(NBODY_EINVAL, "G must be finite");
+  const int64_t n = plan->n_total;
+  if (n == 0) return NBODY_OK;
+  if (!pos || !mass || !acc) return fail(NBODY_EINVAL, "pos, mass and acc must be non-NULL");
+  const size_t b3 = static_cast<size_t>(n) * 3 * sizeof(double), b1 = static_cast<size_t>(n) * sizeof(double);
+  if (overlap(acc, b3, pos, b3) || overlap(acc, b3, mass, b1) || overlap(pot, b1, pos, b3) ||
+      overlap(pot, b1, mass, b1) || overlap(pot, b1, acc, b3))
+    return fail(NBODY_EINVAL, "output arrays overlap inputs or each other");
+  nbody_status st = check_ws(ws, ws_bytes, n, plan->variant);
+  if (st != NBODY_OK) return st;
+  const hipError_t e = enqueue_batched(pos, mass, plan, G, acc, pot, ws, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "nbody_accel_batched launch");
+  return NBODY_OK;
+}
+
+nbody_status nbody_step(double *pos, double *vel, double *acc, double *pot, const double *mass,
+                        int64_t n, double eps, double G, double dt, int32_t n_steps,
+                        int32_t variant, nbody_plan *plan, double *diag, void *ws,
+                        size_t ws_bytes, void *stream) {
+  g_err.clear();
+  if (n < 0) return fail(NBODY_EINVAL, "n must be >= 0");
+  if (n_steps < 0) return fail(NBODY_EINVAL, "n_steps must be >= 0 (got %d)", n_steps);
+  if (!valid_variant(variant)) return fail(NBODY_ENOTSUP, "unknown variant %d", variant);
+  if (!std::isfinite(dt)) return fail(NBODY_EINVAL, "dt must be finite");
+  nbody_status st = plan ? (std::isfinite(G) ? NBODY_OK : fail(NBODY_EINVAL, "G must be finite"))
+                         : check_scalars(eps, G);
+  if (st != NBODY_OK) return st;
+  if (plan) {
+    if (plan->n_total != n)
+      return fail(NBODY_EINVAL, "plan covers %lld particles, n = %lld",
+                  static_cast<long long>(plan->n_total), static_cast<long long>(n));
+    if (plan->variant != variant)
+      return fail(NBODY_EINVAL, "variant %d does not match the plan's %d", variant, plan->variant);
+  }
+  if (n == 0 || n_steps == 0) return NBODY_OK;
+  if (!pos || !vel || !acc || !mass) return fail(NBODY_EINVAL, "pos, vel, acc and mass must be non-NULL");
+  const size_t b3 = static_cast<size_t>(n) * 3 * sizeof(double), b1 = static_cast<size_t>(n) * sizeof(double);
+  if (overlap(pos, b3, vel, b3) || overlap(pos, b3, acc, b3) || overlap(vel, b3, acc, b3) ||
+      overlap(pos, b3, mass, b1) || overlap(vel, b3, mass, b1) || overlap(acc, b3, mass, b1) ||
+      overlap(pot, b1, pos, b3) || overlap(pot, b1, vel, b3) || overlap(pot, b1, acc, b3) ||
+      overlap(pot, b1, mass, b1))
+    return fail(NBODY_EINVAL, "arrays overlap");
+  if (diag && (overlap(diag, static_cast<size_t>(n_steps) * nb::kDiagLen * sizeof(double), pos, b3) ||
+               overlap(diag, static_cast<size_t>(n_steps) * nb::kDiagLen * sizeof(double), vel, b3) ||
+               overlap(diag, static_cast<size_t>(n_steps) * nb::kDiagLen * sizeof(double), acc, b3)))
+    return fail(NBODY_EINVAL, "diag overlaps the state arrays");
+  st = check_ws(ws, ws_bytes, n, variant);
+  if (st != NBODY_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const WsLayout L = ws_layout(n, variant);
+  hipError_t e = hipSuccess;
+  if (diag) e = nb::launch_fill_int(at<int>(ws, L.ctr), 1, 0, s);
+  if (e != hipSuccess) return hip_fail(e, "nbody_step");
+
+  if (!plan) {
+    for (int32_t k = 0; k < n_steps && e == hipSuccess; ++k)
+      e = enqueue_step(pos, vel, acc, pot, mass, n, eps, G, dt, variant, nullptr, diag, ws, s);
+    if (e != hipSuccess) return hip_fail(e, "nbody_step launch");
+    return NBODY_OK;
+  }
+
+  // Batched: capture one step as a graph (once per argument set), replay it.
+  const void *key[9] = {pos, vel, acc, pot, mass, diag, ws, nullptr, nullptr};
+  const bool same = plan->exec && std::memcmp(key, plan->key, sizeof(key)) == 0 &&
+                    plan->key_g == G && plan->key_dt == dt;
+  if (!same) {
+    if (plan->exec) {
+      (void)hipGraphExecDestroy(plan->exec);
+      plan->exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(plan->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    const hipError_t le = enqueue_step(pos, vel, acc, pot, mass, n, 0.0, G, dt, variant, plan,
+                                       diag, ws, plan->capture);
+    e = hipStreamEndCapture(plan->capture, &graph);
+    if (le != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(le, "graph capture of a step");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&plan->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      plan->exec = nullptr;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    std::memcpy(plan->key, key, sizeof(key));
+    plan->key_g = G;
+    plan->key_dt = dt;
+  }
+  for (int32_t k = 0; k < n_steps && e == hipSuccess; ++k) e = hipGraphLaunch(plan->exec, s);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return NBODY_OK;
+}
+
+int32_t nbody_tune_count(int32_t variant) {
+  return valid_variant(variant) ? nb::single_cfg_count() : 0;
+}
+
+nbody_status nbody_tune_describe(int32_t variant, int32_t cfg, int32_t *out6) {
+  g_err.clear();
+  if (!valid_variant(variant)) return fail(NBODY_ENOTSUP, "unknown variant %d", variant);
+  if (!out6) return fail(NBODY_EINVAL, "out6 is NULL");
+  if (cfg >= 1000) {  // batched modes are described as 1000 + mode
+    const int m = cfg - 1000;
+    if (m >= nb::batched_mode_count()) return fail(NBODY_EINVAL, "no batched mode %d", m);
+    const nb::PairCfg &c = nb::batched_mode(m);
+    const int32_t v[6] = {c.block, c.k, c.ls, c.sw, c.tile, nb::cfg_iblock(c)};
+    std::memcpy(out6, v, sizeof(v));
+    return NBODY_OK;
+  }
+  if (cfg < 0 || cfg >= nb::single_cfg_count()) return fail(NBODY_EINVAL, "no configuration %d", cfg);
+  const nb::PairCfg &c = nb::single_cfg(cfg);
+  const int32_t v[6] = {c.block, c.k, c.ls, c.sw, c.tile, nb::cfg_iblock(c)};
+  std::memcpy(out6, v, sizeof(v));
+  return NBODY_OK;
+}
+
+// cfg encodes config + 1000 * split; -1 restores the table entry.
+nbody_status nbody_tune_set(int32_t variant, int32_t size_class_, int32_t cfg) {
+  g_err.clear();
+  if (!valid_variant(variant)) return fail(NBODY_ENOTSUP, "unknown variant %d", variant);
+  if (size_class_ < 0 || size_class_ >= kClasses) return fail(NBODY_EINVAL, "size class out of range");
+  if (cfg != -1) {
+    const int c = cfg % 1000, sp = cfg / 1000;
+    if (c < 0 || c >= nb::single_cfg_count() || sp < 0 || sp > nb::kMaxSplit)
+      return fail(NBODY_EINVAL, "bad configuration %d", cfg);
+  }
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_init_locked();
+  g_forced[variant][size_class_] = cfg;
+  return NBODY_OK;
+}
+
+int32_t nbody_tune_get(int32_t variant, int64_t n) {
+  if (!valid_variant(variant) || n < 0) return -1;
+  const SingleTune t = single_tune(variant, n);
+  return t.cfg + 1000 * t.split;
+}
+
+nbody_status nbody_tune_load(const char *path) {
+  g_err.clear();
+  if (!path) return fail(NBODY_EINVAL, "path is NULL");
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_init_locked();
+  return tune_load_locked(path);
+}
+
+nbody_status nbody_timing_enable(int32_t on) {
+  g_err.clear();
+  g_timing.on = on != 0;
+  g_timing.used = 0;
+  return NBODY_OK;
+}
+
+nbody_status nbody_timing_read(int64_t *launches, double *total_ms) {
+  g_err.clear();
+  if (!launches || !total_ms) return fail(NBODY_EINVAL, "launches and total_ms must be non-NULL");
+  double sum = 0.0;
+  int64_t count = 0;
+  for (size_t k = 0; k + 1 < g_timing.used; k += 2) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(g_timing.pool[k + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, g_timing.pool[k], g_timing.pool[k + 1]);
+    if (e != hipSuccess) {
+      g_timing.used = 0;
+      return hip_fail(e, "nbody_timing_read");
+    }
+    sum += ms;
+    ++count;
+  }
+  g_timing.used = 0;
+  *launches = count;
+  *total_ms = sum;
+  return NBODY_OK;
+}
+
+nbody_status nbody_tune_reset(void) {
+  g_err.clear();
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune_init = false;
+  tune_init_locked();
+  return NBODY_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,741 @@
+// HIP kernels for gfx950 (MI355X): softened all-pairs gravity, FP64
+// kick-drift-kick leapfrog and FP64 diagnostics.
+//
+// Pair sum: the force equation of Section 3 (sum over j != i of
+// G m_j (r_j - r_i) / r_ij^3 per unit target mass) with Plummer softening,
+// plus the potential. The pair arithmetic is FP32 on the vector ALUs, one
+// hardware reciprocal square root per pair; there is no dense contraction, so
+// no matrix cores. Layout of the work:
+//   * a block covers an i-block; each thread holds K i-particles in VGPRs;
+//   * j-particles are streamed through LDS in tiles (double buffered: the
+//     global loads of tile t+1 are in flight while tile t is consumed, one
+//     barrier per tile); a wave reads a j-entry as an LDS broadcast;
+//   * LS lanes may share one i (each takes every LS-th j of a tile) and SW
+//     waves may share one i-group (each takes its own slice of a tile); the
+//     partial sums are then combined by lane shuffles and through LDS, in a
+//     fixed order, so results are bitwise reproducible;
+//   * sums are two-level: a plain FP32 partial per tile, merged into the
+//     running sum once per tile (plain form) or by TwoSum into a (hi, lo)
+//     pair (compensated form).
+// The compensated form stages j-particles from the FP64 inputs as
+// double-single coordinates relative to an FP64 frame (the first i of the
+// block): hi = fp32(x - c), lo = fp32((x - c) - hi); a separation is
+// (hi_j - hi_i) + (lo_j - lo_i).
+#include "nbody_internal.h"
+
+namespace nb {
+
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Knuth's TwoSum: s + e == a + b exactly (round-to-nearest, no overflow).
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Destination of a block's results.
+struct OutArgs {
+  double *acc;       // [n][3] or nullptr when writing partials
+  double *pot;       // [n] or nullptr
+  float4 *part;      // grid j-split partials, nullptr when writing acc/pot
+  int64_t n;         // stride of one split in `part`
+  int split_index;
+  double G;
+};
+
+// Self-pair term the kernel adds to the potential sum when eps > 0 (the pair
+// j == i contributes m_i * rsq(eps^2) and nothing to the acceleration); it is
+// removed again in FP64. The expression matches the in-loop one bit for bit.
+__device__ __forceinline__ float self_term(float m, float eps2f) { return m * rsq(eps2f); }
+
+template <bool COMP>
+struct StageRegs;
+template <>
+struct StageRegs<false> {
+  float4 v;
+};
+template <>
+struct StageRegs<true> {
+  double x, y, z, m;
+};
+
+template <bool COMP>
+__device__ __forceinline__ void stage_load(StageRegs<COMP> &r, const double *__restrict__ pos,
+                                           const double *__restrict__ mass,
+                                           const float4 *__restrict__ packed, int64_t j, bool valid,
+                                           double cx, double cy, double cz) {
+  if constexpr (COMP) {
+    if (valid) {
+      r.x = pos[3 * j];
+      r.y = pos[3 * j + 1];
+      r.z = pos[3 * j + 2];
+      r.m = mass[j];
+    } else {
+      r.x = cx;
+      r.y = cy;
+      r.z = cz;
+      r.m = 0.0;
+    }
+  } else {
+    r.v = valid ? packed[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+__device__ __forceinline__ void ds_split(double d, float &hi, float &lo) {
+  hi = static_cast<float>(d);
+  lo = static_cast<float>(d - static_cast<double>(hi));
+}
+
+template <bool COMP>
+__device__ __forceinline__ void stage_store(float4 *dst, const StageRegs<COMP> &r, double cx,
+                                            double cy, double cz) {
+  if constexpr (COMP) {
+    float hx, hy, hz, lx, ly, lz;
+    ds_split(r.x - cx, hx, lx);
+    ds_split(r.y - cy, hy, ly);
+    ds_split(r.z - cz, hz, lz);
+    dst[0] = make_float4(hx, hy, hz, static_cast<float>(r.m));
+    dst[1] = make_float4(lx, ly, lz, 0.f);
+  } else {
+    dst[0] = r.v;
+  }
+}
+
+// One block computes the i-particles [i0, i1) against the j-particles
+// [j0, j1). `lds` holds 2 * TILE * (COMP ? 2 : 1) float4.
+template <int BLOCK, int K, int LS, int SW, int TILE, bool COMP, bool EPS0>
+__device__ __forceinline__ void pair_block(const double *__restrict__ pos,
+                                           const double *__restrict__ mass,
+                                           const float4 *__restrict__ packed, int64_t i0,
+                                           int64_t i1, int64_t j0, int64_t j1, float eps2f,
+                                           float4 *lds, const OutArgs &o) {
+  constexpr int NW = BLOCK / 64;
+  constexpr int NG = NW / SW;       // i-groups per block
+  constexpr int IPW = 64 / LS;      // i's per wave for one k
+  constexpr int Q = SW * LS;        // j sub-streams per i
+  constexpr int JPT = TILE / Q;     // j's per thread per tile
+  constexpr int JW = COMP ? 2 : 1;  // float4 words per staged j
+  constexpr int SPT = TILE / BLOCK; // j's each thread stages per tile
+  static_assert(BLOCK % 64 == 0 && NW % SW == 0 && 64 % LS == 0, "bad block shape");
+  static_assert(TILE % BLOCK == 0 && TILE % Q == 0, "bad tile");
+  static_assert((SW - 1) * NG * IPW * K * 4 * JW <= 2 * TILE * JW * 4, "combine does not fit in LDS");
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wj = wave % SW, wg = wave / SW;
+  const int lj = lane % LS, li = lane / LS;
+  const int q = wj * LS + lj;
+
+  double cx = 0.0, cy = 0.0, cz = 0.0;
+  if constexpr (COMP) {
+    cx = pos[3 * i0];
+    cy = pos[3 * i0 + 1];
+    cz = pos[3 * i0 + 2];
+  }
+
+  float xh[K], yh[K], zh[K], xl[K], yl[K], zl[K], mi[K];
+  int64_t iidx[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t i = i0 + static_cast<int64_t>(k) * (NG * IPW) + wg * IPW + li;
+    iidx[k] = i;
+    const int64_t ic = i < i1 ? i : i1 - 1;
+    if constexpr (COMP) {
+      ds_split(pos[3 * ic] - cx, xh[k], xl[k]);
+      ds_split(pos[3 * ic + 1] - cy, yh[k], yl[k]);
+      ds_split(pos[3 * ic + 2] - cz, zh[k], zl[k]);
+    } else {
+      xh[k] = static_cast<float>(pos[3 * ic]);
+      yh[k] = static_cast<float>(pos[3 * ic + 1]);
+      zh[k] = static_cast<float>(pos[3 * ic + 2]);
+      xl[k] = yl[k] = zl[k] = 0.f;
+    }
+    mi[k] = static_cast<float>(mass[ic]);
+  }
+
+  float ah[K][4], al[K][4];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ah[k][c] = al[k][c] = 0.f;
+
+  const int64_t ntiles = j1 > j0 ? (j1 - j0 + TILE - 1) / TILE : 0;
+  StageRegs<COMP> sr[SPT];
+
+  if (ntiles > 0) {
+#pragma unroll
+    for (int r = 0; r < SPT; ++r) {
+      const int64_t j = j0 + r * BLOCK + tid;
+      stage_load<COMP>(sr[r], pos, mass, packed, j, j < j1, cx, cy, cz);
+    }
+#pragma unroll
+    for (int r = 0; r < SPT; ++r) stage_store<COMP>(lds + (r * BLOCK + tid) * JW, sr[r], cx, cy, cz);
+  }
+  __syncthreads();
+
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const int buf = static_cast<int>(t & 1);
+    const bool more = t + 1 < ntiles;
+    if (more) {
+#pragma unroll
+      for (int r = 0; r < SPT; ++r) {
+        const int64_t j = j0 + (t + 1) * TILE + r * BLOCK + tid;
+        stage_load<COMP>(sr[r], pos, mass, packed, j, j < j1, cx, cy, cz);
+      }
+    }
+
+    const float4 *T = lds + buf * (TILE * JW);
+    float p[K][4];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) p[k][c] = 0.f;
+
+#pragma unroll 8
+    for (int jj = 0; jj < JPT; ++jj) {
+      const int jl = jj * Q + q;
+      const float4 H = T[jl * JW];
+      float4 L = make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (COMP) L = T[jl * JW + 1];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        float dx, dy, dz;
+        if constexpr (COMP) {
+          dx = (H.x - xh[k]) + (L.x - xl[k]);
+          dy = (H.y - yh[k]) + (L.y - yl[k]);
+          dz = (H.z - zh[k]) + (L.z - zl[k]);
+        } else {
+          dx = H.x - xh[k];
+          dy = H.y - yh[k];
+          dz = H.z - zh[k];
+        }
+        float r2 = fmaf(dx, dx, eps2f);
+        r2 = fmaf(dy, dy, r2);
+        r2 = fmaf(dz, dz, r2);
+        float rho = rsq(r2);
+        if constexpr (EPS0) rho = r2 > 0.f ? rho : 0.f;
+        const float mr = H.w * rho;
+        const float s = mr * (rho * rho);
+        p[k][0] = fmaf(s, dx, p[k][0]);
+        p[k][1] = fmaf(s, dy, p[k][1]);
+        p[k][2] = fmaf(s, dz, p[k][2]);
+        p[k][3] += mr;
+      }
+    }
+
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if constexpr (COMP) {
+          float s, e;
+          two_sum(ah[k][c], p[k][c], s, e);
+          ah[k][c] = s;
+          al[k][c] += e;
+        } else {
+          ah[k][c] += p[k][c];
+        }
+      }
+
+    if (more) {
+      float4 *D = lds + (buf ^ 1) * (TILE * JW);
+#pragma unroll
+      for (int r = 0; r < SPT; ++r) stage_store<COMP>(D + (r * BLOCK + tid) * JW, sr[r], cx, cy, cz);
+    }
+    __syncthreads();
+  }
+
+  // Lanes sharing an i: butterfly over the low lane bits (fixed order).
+#pragma unroll
+  for (int off = 1; off < LS; off <<= 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float oh = __shfl_xor(ah[k][c], off, 64);
+        if constexpr (COMP) {
+          const float ol = __shfl_xor(al[k][c], off, 64);
+          float s, e;
+          two_sum(ah[k][c], oh, s, e);
+          ah[k][c] = s;
+          al[k][c] = (al[k][c] + ol) + e;
+        } else {
+          ah[k][c] += oh;
+        }
+      }
+  }
+
+  // Waves sharing an i-group: waves 1..SW-1 park their sums in LDS, wave 0
+  // adds them in wave order. The tile buffers are free (last barrier above).
+  if constexpr (SW > 1) {
+    float *X = reinterpret_cast<float *>(lds);
+    constexpr int SLOT = NG * IPW * K * 4 * JW;  // floats per parked wave
+    const int base = (wg * IPW + li) * K * 4 * JW;
+    if (wj > 0 && lj == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          X[(wj - 1) * SLOT + base + (k * 4 + c) * JW] = ah[k][c];
+          if constexpr (COMP) X[(wj - 1) * SLOT + base + (k * 4 + c) * JW + 1] = al[k][c];
+        }
+    }
+    __syncthreads();
+    if (wj == 0 && lj == 0) {
+      for (int w = 1; w < SW; ++w) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const float oh = X[(w - 1) * SLOT + base + (k * 4 + c) * JW];
+            if constexpr (COMP) {
+              const float ol = X[(w - 1) * SLOT + base + (k * 4 + c) * JW + 1];
+              float s, e;
+              two_sum(ah[k][c], oh, s, e);
+              ah[k][c] = s;
+              al[k][c] = (al[k][c] + ol) + e;
+            } else {
+              ah[k][c] += oh;
+            }
+          }
+      }
+    }
+    __syncthreads();
+  }
+
+  if (wj != 0 || lj != 0) return;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t i = iidx[k];
+    if (i >= i1) continue;
+    if (o.part) {
+      float4 *P = o.part + (static_cast<int64_t>(o.split_index) * o.n + i) * JW;
+      P[0] = make_float4(ah[k][0], ah[k][1], ah[k][2], ah[k][3]);
+      if constexpr (COMP) P[1] = make_float4(al[k][0], al[k][1], al[k][2], al[k][3]);
+    } else {
+      double s[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        s[c] = COMP ? static_cast<double>(ah[k][c]) + static_cast<double>(al[k][c])
+                    : static_cast<double>(ah[k][c]);
+      o.acc[3 * i] = o.G * s[0];
+      o.acc[3 * i + 1] = o.G * s[1];
+      o.acc[3 * i + 2] = o.G * s[2];
+      if (o.pot) {
+        const double self = EPS0 ? 0.0 : static_cast<double>(self_term(mi[k], eps2f));
+        o.pot[i] = -o.G * (s[3] - self);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Single system.
+
+template <int BLOCK, int K, int LS, int SW, int TILE, bool COMP, bool EPS0>
+__global__ __launch_bounds__(BLOCK) void pair_single_kernel(
+    const double *__restrict__ pos, const double *__restrict__ mass,
+    const float4 *__restrict__ packed, int64_t n, float eps2f, int split, int64_t split_len,
+    OutArgs o) {
+  constexpr int JW = COMP ? 2 : 1;
+  __shared__ float4 lds[2 * TILE * JW];
+  constexpr int IB = (BLOCK / 64 / SW) * (64 / LS) * K;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * IB;
+  const int64_t i1 = i0 + IB < n ? i0 + IB : n;
+  const int s = blockIdx.y;
+  const int64_t j0 = static_cast<int64_t>(s) * split_len;
+  const int64_t j1 = j0 + split_len < n ? j0 + split_len : n;
+  OutArgs oo = o;
+  oo.split_index = s;
+  pair_block<BLOCK, K, LS, SW, TILE, COMP, EPS0>(pos, mass, packed, i0, i1, j0, j1, eps2f, lds,
+                                                  oo);
+}
+
+// Sums the grid j-split partials in split order (FP64) and applies G and the
+// self-term correction.
+template <bool COMP>
+__global__ __launch_bounds__(256) void combine_kernel(const float4 *__restrict__ part, int split,
+                                                      int64_t n, const double *__restrict__ mass,
+                                                      float eps2f, int eps0, double G,
+                                                      double *__restrict__ acc,
+                                                      double *__restrict__ pot) {
+  constexpr int JW = COMP ? 2 : 1;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int s = 0; s < split; ++s) {
+    const float4 *P = part + (static_cast<int64_t>(s) * n + i) * JW;
+    const float4 h = P[0];
+    s0 += h.x;
+    s1 += h.y;
+    s2 += h.z;
+    s3 += h.w;
+    if constexpr (COMP) {
+      const float4 l = P[1];
+      s0 += l.x;
+      s1 += l.y;
+      s2 += l.z;
+      s3 += l.w;
+    }
+  }
+  acc[3 * i] = G * s0;
+  acc[3 * i + 1] = G * s1;
+  acc[3 * i + 2] = G * s2;
+  if (pot) {
+    const double self = eps0 ? 0.0 : static_cast<double>(self_term(static_cast<float>(mass[i]), eps2f));
+    pot[i] = -G * (s3 - self);
+  }
+}
+
+__global__ __launch_bounds__(256) void pack_kernel(const double *__restrict__ pos,
+                                                   const double *__restrict__ mass, int64_t n,
+                                                   float4 *__restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  out[i] = make_float4(static_cast<float>(pos[3 * i]), static_cast<float>(pos[3 * i + 1]),
+                       static_cast<float>(pos[3 * i + 2]), static_cast<float>(mass[i]));
+}
+
+// Compiled single-system configurations: {block, k, ls, sw, tile}.
+static const PairCfg kSingle[] = {
+    {256, 1, 1, 1, 256},   // 0
+    {256, 2, 1, 1, 256},   // 1
+    {256, 4, 1, 1, 256},   // 2
+    {256, 2, 1, 2, 512},   // 3
+    {256, 1, 1, 4, 1024},  // 4
+    {256, 1, 4, 1, 256},   // 5
+    {256, 4, 1, 2, 512},   // 6
+    {256, 2, 1, 4, 1024},  // 7
+    {256, 8, 1, 1, 256},   // 8
+    {256, 2, 2, 1, 512},   // 9
+};
+int single_cfg_count() { return static_cast<int>(sizeof(kSingle) / sizeof(kSingle[0])); }
+const PairCfg &single_cfg(int idx) { return kSingle[idx]; }
+
+template <int BLOCK, int K, int LS, int SW, int TILE>
+static hipError_t launch_single_t(bool comp, bool eps0, dim3 grid, const double *pos,
+                                  const double *mass, const float4 *packed, int64_t n,
+                                  float eps2f, int split, int64_t split_len, const OutArgs &o,
+                                  hipStream_t st) {
+  if (comp) {
+    if (eps0)
+      pair_single_kernel<BLOCK, K, LS, SW, TILE, true, true>
+          <<<grid, BLOCK, 0, st>>>(pos, mass, packed, n, eps2f, split, split_len, o);
+    else
+      pair_single_kernel<BLOCK, K, LS, SW, TILE, true, false>
+          <<<grid, BLOCK, 0, st>>>(pos, mass, packed, n, eps2f, split, split_len, o);
+  } else {
+    if (eps0)
+      pair_single_kernel<BLOCK, K, LS, SW, TILE, false, true>
+          <<<grid, BLOCK, 0, st>>>(pos, mass, packed, n, eps2f, split, split_len, o);
+    else
+      pair_single_kernel<BLOCK, K, LS, SW, TILE, false, false>
+          <<<grid, BLOCK, 0, st>>>(pos, mass, packed, n, eps2f, split, split_len, o);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const double *pos, const double *mass, int64_t n, float4 *packed,
+                       hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
+  pack_kernel<<<blocks, 256, 0, stream>>>(pos, mass, n, packed);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_single(int cfg, bool comp, const double *pos, const double *mass,
+                              const float4 *packed, int64_t n, double eps, double G, int split,
+                              double *acc, double *pot, float4 *part, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const PairCfg &c = kSingle[cfg];
+  const int64_t ib = cfg_iblock(c);
+  const int64_t nblk = (n + ib - 1) / ib;
+  if (split < 1) split = 1;
+  // Each split covers a whole number of tiles.
+  int64_t split_len = (n + split - 1) / split;
+  split_len = (split_len + c.tile - 1) / c.tile * c.tile;
+  const float eps2f = static_cast<float>(eps * eps);
+  const bool eps0 = eps == 0.0;
+  OutArgs o{};
+  o.G = G;
+  o.n = n;
+  if (split > 1) {
+    o.part = part;
+  } else {
+    o.acc = acc;
+    o.pot = pot;
+  }
+  dim3 grid(static_cast<unsigned>(nblk), static_cast<unsigned>(split));
+  hipError_t e;
+  switch (cfg) {
+#define NB_CASE(I, B, K, LS, SW, T) \
+  case I: e = launch_single_t<B, K, LS, SW, T>(comp, eps0, grid, pos, mass, packed, n, eps2f, split, split_len, o, stream); break;
+    NB_CASE(0, 256, 1, 1, 1, 256)
+    NB_CASE(1, 256, 2, 1, 1, 256)
+    NB_CASE(2, 256, 4, 1, 1, 256)
+    NB_CASE(3, 256, 2, 1, 2, 512)
+    NB_CASE(4, 256, 1, 1, 4, 1024)
+    NB_CASE(5, 256, 1, 4, 1, 256)
+    NB_CASE(6, 256, 4, 1, 2, 512)
+    NB_CASE(7, 256, 2, 1, 4, 1024)
+    NB_CASE(8, 256, 8, 1, 1, 256)
+    NB_CASE(9, 256, 2, 2, 1, 512)
+#undef NB_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess || split == 1) return e;
+  const unsigned cb = static_cast<unsigned>((n + 255) / 256);
+  if (comp)
+    combine_kernel<true><<<cb, 256, 0, stream>>>(part, split, n, mass, eps2f, eps0 ? 1 : 0, G, acc, pot);
+  else
+    combine_kernel<false><<<cb, 256, 0, stream>>>(part, split, n, mass, eps2f, eps0 ? 1 : 0, G, acc, pot);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched: a persistent grid claims (cluster, i-block) work items, heaviest
+// first, from a global counter.
+
+static const PairCfg kBatched[] = {
+    {256, 1, 1, 4, 512},  // 0: 64 i per item, j split over 4 waves
+    {256, 1, 1, 2, 512},  // 1: 128 i per item
+    {256, 2, 1, 2, 512},  // 2: 256 i per item
+    {256, 2, 1, 1, 256},  // 3: 512 i per item
+};
+int batched_mode_count() { return static_cast<int>(sizeof(kBatched) / sizeof(kBatched[0])); }
+const PairCfg &batched_mode(int idx) { return kBatched[idx]; }
+
+template <bool COMP, bool EPS0>
+__device__ __forceinline__ void batched_dispatch(int mode, const double *__restrict__ pos,
+                                                 const double *__restrict__ mass,
+                                                 const float4 *__restrict__ packed, int64_t i0,
+                                                 int64_t i1, int64_t j0, int64_t j1, float eps2f,
+                                                 float4 *lds, const OutArgs &o) {
+  switch (mode) {
+    case 0: pair_block<256, 1, 1, 4, 512, COMP, EPS0>(pos, mass, packed, i0, i1, j0, j1, eps2f, lds, o); break;
+    case 1: pair_block<256, 1, 1, 2, 512, COMP, EPS0>(pos, mass, packed, i0, i1, j0, j1, eps2f, lds, o); break;
+    case 2: pair_block<256, 2, 1, 2, 512, COMP, EPS0>(pos, mass, packed, i0, i1, j0, j1, eps2f, lds, o); break;
+    default: pair_block<256, 2, 1, 1, 256, COMP, EPS0>(pos, mass, packed, i0, i1, j0, j1, eps2f, lds, o); break;
+  }
+}
+
+template <bool COMP>
+__global__ __launch_bounds__(256) void pair_batched_kernel(
+    const double *__restrict__ pos, const double *__restrict__ mass,
+    const float4 *__restrict__ packed, const Item *__restrict__ items, int32_t n_items, const double *__restrict__ eps_k, double G,
+    int *__restrict__ counters, double *__restrict__ acc, double *__restrict__ pot) {
+  __shared__ float4 lds[2 * 512 * 2];
+  __shared__ int s_item;
+  OutArgs o{};
+  o.acc = acc;
+  o.pot = pot;
+  o.G = G;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&counters[0], 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= n_items) break;
+    const Item d = items[it];
+    const double eps = eps_k[d.cluster];
+    const float eps2f = static_cast<float>(eps * eps);
+    if (eps == 0.0)
+      batched_dispatch<COMP, true>(d.mode, pos, mass, packed, d.i0, d.i1, d.j0, d.j1, eps2f, lds, o);
+    else
+      batched_dispatch<COMP, false>(d.mode, pos, mass, packed, d.i0, d.i1, d.j0, d.j1, eps2f, lds, o);
+    __syncthreads();
+  }
+}
+
+hipError_t launch_pair_batched(bool comp, const double *pos, const double *mass,
+                               float4 *packed, int64_t n_total, const Item *items,
+                               int32_t n_items, const double *eps_k, double G, int grid,
+                               int *counters, double *acc, double *pot, hipStream_t stream) {
+  hipError_t e = launch_fill_int(counters, 2, 0, stream);
+  if (e != hipSuccess || n_items == 0) return e;
+  if (comp) {
+    pair_batched_kernel<true><<<grid, 256, 0, stream>>>(pos, mass, nullptr, items, n_items, eps_k,
+                                                        G, counters, acc, pot);
+  } else {
+    e = launch_pack(pos, mass, n_total, packed, stream);
+    if (e != hipSuccess) return e;
+    pair_batched_kernel<false><<<grid, 256, 0, stream>>>(pos, mass, packed, items, n_items, eps_k,
+                                                         G, counters, acc, pot);
+  }
+  return hipGetLastError();
+}
+
+int batched_grid(bool comp) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const hipError_t e =
+      comp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pair_batched_kernel<true>, 256, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pair_batched_kernel<false>, 256, 0);
+  if (e != hipSuccess) return 0;
+  if (per < 1) per = 1;
+  return cus * per;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 leapfrog and diagnostics.
+
+__global__ __launch_bounds__(256) void kick_drift_kernel(double *__restrict__ pos,
+                                                         double *__restrict__ vel,
+                                                         const double *__restrict__ acc,
+                                                         int64_t n3, double h, double dt) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; k < n3; k += stride) {
+    const double v = vel[k] + h * acc[k];
+    vel[k] = v;
+    pos[k] = pos[k] + dt * v;
+  }
+}
+
+__global__ __launch_bounds__(256) void kick_kernel(double *__restrict__ vel,
+                                                   const double *__restrict__ acc, int64_t n3,
+                                                   double h) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; k < n3; k += stride)
+    vel[k] = vel[k] + h * acc[k];
+}
+
+static unsigned elementwise_blocks(int64_t n3) {
+  int64_t b = (n3 + 255) / 256;
+  if (b > 8192) b = 8192;
+  return static_cast<unsigned>(b < 1 ? 1 : b);
+}
+
+hipError_t launch_kick_drift(double *pos, double *vel, const double *acc, int64_t n, double h,
+                             double dt, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  kick_drift_kernel<<<elementwise_blocks(3 * n), 256, 0, stream>>>(pos, vel, acc, 3 * n, h, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_kick(double *vel, const double *acc, int64_t n, double h, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  kick_kernel<<<elementwise_blocks(3 * n), 256, 0, stream>>>(vel, acc, 3 * n, h);
+  return hipGetLastError();
+}
+
+// Quantities reduced for one diagnostics row, before the final pass.
+constexpr int kRed = 13;  // K, W, P[3], L[3], sum m x [3], M, non-finite count
+
+__device__ __forceinline__ void block_reduce(double (*sm)[kDiagThreads], double *v) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kRed; ++q) sm[q][t] = v[q];
+  __syncthreads();
+  for (int w = kDiagThreads / 2; w > 0; w >>= 1) {
+    if (t < w) {
+#pragma unroll
+      for (int q = 0; q < kRed; ++q) sm[q][t] += sm[q][t + w];
+    }
+    __syncthreads();
+  }
+}
+
+// v += h a for every particle, then per-block partial diagnostics of the
+// kicked state; one row of kDiagLen doubles per block.
+__global__ __launch_bounds__(kDiagThreads) void kick_diag_kernel(
+    const double *__restrict__ pos, double *__restrict__ vel, const double *__restrict__ acc,
+    const double *__restrict__ pot, const double *__restrict__ mass, int64_t n, double h,
+    int do_kick, double *__restrict__ partial) {
+  __shared__ double sm[kRed][kDiagThreads];
+  double v[kRed];
+#pragma unroll
+  for (int q = 0; q < kRed; ++q) v[q] = 0.0;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kDiagThreads;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kDiagThreads + threadIdx.x; i < n;
+       i += stride) {
+    double vx = vel[3 * i], vy = vel[3 * i + 1], vz = vel[3 * i + 2];
+    if (do_kick) {
+      vx = vx + h * acc[3 * i];
+      vy = vy + h * acc[3 * i + 1];
+      vz = vz + h * acc[3 * i + 2];
+      vel[3 * i] = vx;
+      vel[3 * i + 1] = vy;
+      vel[3 * i + 2] = vz;
+    }
+    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    const double m = mass[i];
+    v[0] += 0.5 * m * (vx * vx + vy * vy + vz * vz);
+    v[1] += 0.5 * m * pot[i];
+    v[2] += m * vx;
+    v[3] += m * vy;
+    v[4] += m * vz;
+    v[5] += m * (y * vz - z * vy);
+    v[6] += m * (z * vx - x * vz);
+    v[7] += m * (x * vy - y * vx);
+    v[8] += m * x;
+    v[9] += m * y;
+    v[10] += m * z;
+    v[11] += m;
+    v[12] += (isfinite(x) ? 0.0 : 1.0) + (isfinite(y) ? 0.0 : 1.0) + (isfinite(z) ? 0.0 : 1.0) +
+             (isfinite(vx) ? 0.0 : 1.0) + (isfinite(vy) ? 0.0 : 1.0) + (isfinite(vz) ? 0.0 : 1.0);
+  }
+  block_reduce(sm, v);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < kRed; ++q) partial[blockIdx.x * kDiagLen + q] = sm[q][0];
+  }
+}
+
+__global__ __launch_bounds__(kDiagThreads) void diag_final_kernel(const double *__restrict__ partial,
+                                                                  double *__restrict__ diag,
+                                                                  int *__restrict__ step_ctr) {
+  __shared__ double sm[kRed][kDiagThreads];
+  double v[kRed];
+#pragma unroll
+  for (int q = 0; q < kRed; ++q) v[q] = 0.0;
+  for (int b = threadIdx.x; b < kDiagBlocks; b += kDiagThreads) {
+#pragma unroll
+    for (int q = 0; q < kRed; ++q) v[q] += partial[b * kDiagLen + q];
+  }
+  block_reduce(sm, v);
+  if (threadIdx.x == 0) {
+    const int s = *step_ctr;
+    double *row = diag + static_cast<int64_t>(s) * kDiagLen;
+    const double K = sm[0][0], W = sm[1][0], M = sm[11][0];
+    row[0] = K;
+    row[1] = W;
+    row[2] = K + W;
+    for (int q = 0; q < 6; ++q) row[3 + q] = sm[2 + q][0];
+    for (int q = 0; q < 3; ++q) row[9 + q] = sm[8 + q][0] / M;
+    row[12] = M;
+    row[13] = sm[12][0];
+    row[14] = static_cast<double>(s + 1);
+    row[15] = 0.0;
+    *step_ctr = s + 1;
+  }
+}
+
+hipError_t launch_kick_diag(const double *pos, double *vel, const double *acc, const double *pot,
+                            const double *mass, int64_t n, double h, double *partial,
+                            hipStream_t stream) {
+  kick_diag_kernel<<<kDiagBlocks, kDiagThreads, 0, stream>>>(pos, vel, acc, pot, mass, n, h,
+                                                             acc ? 1 : 0, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_final(const double *partial, double *diag, int *step_ctr,
+                             hipStream_t stream) {
+  diag_final_kernel<<<1, kDiagThreads, 0, stream>>>(partial, diag, step_ctr);
+  return hipGetLastError();
+}
+
+__global__ void fill_int_kernel(int *p, int n, int value) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+hipError_t launch_fill_int(int *p, int n, int value, hipStream_t stream) {
+  fill_int_kernel<<<(n + 63) / 64, 64, 0, stream>>>(p, n, value);
+  return hipGetLastError();
+}
+
+}  // namespace nb

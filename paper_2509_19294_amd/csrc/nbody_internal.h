@@ -1,0 +1,77 @@
+// Internal interface between the C ABI (abi.cpp) and the HIP kernels
+// (kernels.hip). Not installed; the public contract is include/nbody.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace nb {
+
+constexpr int kDiagLen = 16;
+constexpr int kMaxSplit = 8;          // largest grid-level j-split
+constexpr int kDiagBlocks = 512;      // blocks of the first diagnostics pass
+constexpr int kDiagThreads = 256;
+
+// One compiled pair-kernel configuration.
+struct PairCfg {
+  int block;  // threads per block (multiple of 64)
+  int k;      // i-particles per thread (register blocking)
+  int ls;     // lanes sharing one i (intra-wave j-split, combined by shuffles)
+  int sw;     // waves sharing one i-group (inter-wave j-split, combined in LDS)
+  int tile;   // j-particles staged in LDS per tile
+};
+
+// i-particles one block covers for an item.
+inline int cfg_iblock(const PairCfg &c) { return (c.block / 64 / c.sw) * (64 / c.ls) * c.k; }
+
+// Table of compiled single-system configurations (same table for both forms).
+int single_cfg_count();
+const PairCfg &single_cfg(int idx);
+
+// Batched modes compiled into the persistent kernel.
+int batched_mode_count();
+const PairCfg &batched_mode(int idx);
+
+// Work item of the batched kernel: i in [i0, i1) against j in [j0, j1).
+struct Item {
+  int32_t i0, i1, j0, j1;
+  int32_t cluster;  // index into the per-cluster eps array
+  int32_t mode;     // batched_mode index
+  int32_t pad0, pad1;
+};
+
+// Launchers. All enqueue on `stream` and return the launch status.
+hipError_t launch_pack(const double *pos, const double *mass, int64_t n, float4 *packed,
+                       hipStream_t stream);
+
+// Single system: accelerations (and potentials) of all n particles.
+// `part` must hold split * n * (comp ? 2 : 1) float4 when split > 1.
+hipError_t launch_pair_single(int cfg, bool comp, const double *pos, const double *mass,
+                              const float4 *packed, int64_t n, double eps, double G, int split,
+                              double *acc, double *pot, float4 *part, hipStream_t stream);
+
+// Batched persistent kernel over a work list.
+// `packed` (n_total float4) is scratch for the plain form; `counters` holds
+// two ints (work counter, reserved) reset by a fill kernel before the launch.
+hipError_t launch_pair_batched(bool comp, const double *pos, const double *mass,
+                               float4 *packed, int64_t n_total, const Item *items,
+                               int32_t n_items, const double *eps_k, double G, int grid,
+                               int *counters, double *acc, double *pot, hipStream_t stream);
+int batched_grid(bool comp);  // persistent grid size (blocks) for the current device
+
+// FP64 integrator and diagnostics.
+hipError_t launch_kick_drift(double *pos, double *vel, const double *acc, int64_t n, double h,
+                             double dt, hipStream_t stream);
+hipError_t launch_kick(double *vel, const double *acc, int64_t n, double h, hipStream_t stream);
+// Kick fused with the first diagnostics pass (per-block partial rows).
+hipError_t launch_kick_diag(const double *pos, double *vel, const double *acc, const double *pot,
+                            const double *mass, int64_t n, double h, double *partial,
+                            hipStream_t stream);
+// Second pass: sums the partial rows in a fixed order into diag[*step_ctr],
+// then increments *step_ctr.
+hipError_t launch_diag_final(const double *partial, double *diag, int *step_ctr,
+                             hipStream_t stream);
+hipError_t launch_fill_int(int *p, int n, int value, hipStream_t stream);
+
+}  // namespace nb

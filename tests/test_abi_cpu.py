@@ -1,0 +1,187 @@
+"""Host-side contract of libnbody.so, checked without a GPU.
+
+The library must load, export every function include/nbody.h declares, and
+reject every invalid argument with its status code before any launch (these
+paths touch no device, so fake non-NULL pointers are safe: validation never
+dereferences them).
+"""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_2509_19294_amd import nbody
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nbody.h")
+FAKE = ctypes.c_void_p(0x100000)        # never dereferenced by validation
+FAKE2 = ctypes.c_void_p(0x900000)
+FAKE3 = ctypes.c_void_p(0x1100000)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return nbody.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nbody_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(lib, name), name
+    assert lib.nbody_version().decode().startswith("nbody")
+
+
+def test_workspace_bytes(lib):
+    assert lib.nbody_workspace_bytes(-1, 1, 0) == 0
+    assert lib.nbody_workspace_bytes(10, 0, 0) == 0
+    assert lib.nbody_workspace_bytes(10, 1, 5) == 0
+    a = lib.nbody_workspace_bytes(1000, 1, 0)
+    b = lib.nbody_workspace_bytes(1000, 1, 1)
+    c = lib.nbody_workspace_bytes(2000, 1, 0)
+    assert 0 < a < b and a < c
+    assert a % 256 == 0 and b % 256 == 0
+    # packed float4 + 8 split partials + pot + diag partials + counters
+    assert a >= 1000 * 16 + 8 * 1000 * 16 + 1000 * 8 + 512 * 16 * 8
+    assert lib.nbody_workspace_bytes(0, 1, 0) > 0
+
+
+def _accel(lib, pos=FAKE, mass=FAKE2, n=100, eps=0.01, G=1.0, variant=0, acc=FAKE3, pot=None,
+           ws=None, ws_bytes=None):
+    if ws is None:
+        ws = ctypes.c_void_p(0x7000000)
+    if ws_bytes is None:
+        ws_bytes = lib.nbody_workspace_bytes(max(n, 0), 1, variant if variant in (0, 1) else 0)
+    return lib.nbody_accel(pos, mass, n, eps, G, variant, acc, pot, ws, ws_bytes, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=-1), nbody.EINVAL),
+    (dict(variant=7), nbody.ENOTSUP),
+    (dict(eps=-1e-3), nbody.EINVAL),
+    (dict(eps=math.nan), nbody.EINVAL),
+    (dict(eps=math.inf), nbody.EINVAL),
+    (dict(G=math.inf), nbody.EINVAL),
+    (dict(G=math.nan), nbody.EINVAL),
+    (dict(pos=None), nbody.EINVAL),
+    (dict(mass=None), nbody.EINVAL),
+    (dict(acc=None), nbody.EINVAL),
+    (dict(acc=FAKE), nbody.EINVAL),                     # output overlaps pos
+    (dict(pot=ctypes.c_void_p(0x100000 + 8)), nbody.EINVAL),
+    (dict(ws=ctypes.c_void_p(0)), nbody.EWORKSPACE),
+    (dict(ws_bytes=100), nbody.EWORKSPACE),
+])
+def test_accel_rejects(lib, kw, code):
+    assert _accel(lib, **kw) == code
+    assert lib.nbody_last_error().decode() != ""
+
+
+def test_accel_n0_is_noop(lib):
+    assert _accel(lib, n=0, pos=None, mass=None, acc=None) == nbody.OK
+    assert lib.nbody_last_error().decode() == ""
+
+
+def _step(lib, n=64, n_steps=3, dt=0.01, eps=0.01, G=1.0, variant=0, plan=None, ws_bytes=None,
+          pos=FAKE, vel=ctypes.c_void_p(0x200000), acc=ctypes.c_void_p(0x300000),
+          mass=ctypes.c_void_p(0x400000), diag=None):
+    if ws_bytes is None:
+        ws_bytes = lib.nbody_workspace_bytes(n, 1, variant if variant in (0, 1) else 0)
+    return lib.nbody_step(pos, vel, acc, None, mass, n, eps, G, dt, n_steps, variant, plan, diag,
+                          ctypes.c_void_p(0x7000000), ws_bytes, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=-5), nbody.EINVAL),
+    (dict(n_steps=-1), nbody.EINVAL),
+    (dict(dt=math.nan), nbody.EINVAL),
+    (dict(eps=-1.0), nbody.EINVAL),
+    (dict(G=math.inf), nbody.EINVAL),
+    (dict(variant=3), nbody.ENOTSUP),
+    (dict(vel=None), nbody.EINVAL),
+    (dict(vel=FAKE), nbody.EINVAL),           # vel overlaps pos
+    (dict(diag=ctypes.c_void_p(0x200010)), nbody.EINVAL),  # diag overlaps vel
+    (dict(ws_bytes=10), nbody.EWORKSPACE),
+])
+def test_step_rejects(lib, kw, code):
+    assert _step(lib, **kw) == code
+
+
+def test_step_zero_steps_is_noop(lib):
+    assert _step(lib, n_steps=0) == nbody.OK
+
+
+def _plan(lib, offsets, eps, variant=1):
+    import numpy as np
+    off = np.asarray(offsets, dtype=np.int64)
+    ep = np.asarray(eps, dtype=np.float64)
+    return lib.nbody_plan_create(off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(ep),
+                                 ep.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), variant, None)
+
+
+@pytest.mark.parametrize("offsets,eps,variant", [
+    ([1, 5], [0.1], 1),            # offsets[0] != 0
+    ([0, 5, 3], [0.1, 0.1], 1),    # decreasing
+    ([0, 5], [-0.1], 1),           # negative eps
+    ([0, 5], [math.nan], 1),       # non-finite eps
+    ([0, 5], [0.1], 9),            # unknown variant
+    ([0, 2 ** 31], [0.1], 1),      # too large for a batched plan
+])
+def test_plan_create_rejects(lib, offsets, eps, variant):
+    assert not _plan(lib, offsets, eps, variant)
+    assert lib.nbody_last_error().decode() != ""
+
+
+def test_plan_create_rejects_k0(lib):
+    import numpy as np
+    off = np.zeros(1, dtype=np.int64)
+    ep = np.zeros(1)
+    assert not lib.nbody_plan_create(off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 0,
+                                     ep.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1, None)
+
+
+def test_batched_rejects_null_plan(lib):
+    st = lib.nbody_accel_batched(FAKE, FAKE2, None, 1.0, FAKE3, None, FAKE, 1 << 20, None)
+    assert st == nbody.EINVAL
+
+
+def test_tuning_table(lib, tmp_path):
+    cfgs = nbody.tune_configs("plain")
+    assert len(cfgs) == lib.nbody_tune_count(0) >= 5
+    for block, k, ls, sw, tile, ib in cfgs:
+        assert block % 64 == 0 and tile % block == 0 and tile % (ls * sw) == 0
+        assert ib == (block // 64 // sw) * (64 // ls) * k
+    modes = nbody.batched_modes()
+    assert len(modes) >= 2
+    buf = (ctypes.c_int32 * 6)()
+    assert lib.nbody_tune_describe(0, 999, buf) == nbody.EINVAL
+    assert lib.nbody_tune_describe(5, 0, buf) == nbody.ENOTSUP
+    # forcing and restoring a configuration
+    before = nbody.tune_get("comp", 5000)
+    nbody.tune_set("comp", 12, 3, 2)
+    assert nbody.tune_get("comp", 5000) == (3, 2)
+    nbody.tune_set("comp", 12, -1)
+    assert nbody.tune_get("comp", 5000) == before
+    assert lib.nbody_tune_set(0, 99, 0) == nbody.EINVAL
+    assert lib.nbody_tune_set(0, 3, 55) == nbody.EINVAL
+    # tuning files
+    good = tmp_path / "t.txt"
+    good.write_text("# kind variant class cfg split\nsingle 0 20 2 4\nbatched 1 11 1\n")
+    nbody.tune_load(str(good))
+    assert nbody.tune_get("plain", 1 << 20) == (2, 4)
+    bad = tmp_path / "b.txt"
+    bad.write_text("single 0 20 999 1\n")
+    with pytest.raises(nbody.NbodyError):
+        nbody.tune_load(str(bad))
+    with pytest.raises(nbody.NbodyError):
+        nbody.tune_load(str(tmp_path / "missing.txt"))
+    nbody.tune_reset()
+    assert nbody.tune_get("plain", 1 << 20) == nbody.tune_get("plain", (1 << 20) + 5)
+    assert nbody.tune_get("comp", 5000) == before
