@@ -96,9 +96,11 @@ const char *nbody_version(void);
  *   G finite.
  *   variant NBODY_FP32_PLAIN or NBODY_FP32_COMP.
  *   acc [n][3] f64 out; pot [n] f64 out or NULL.
- *   ws: device workspace of ws_bytes >= nbody_workspace_bytes(n, 1, variant).
+ *   ws: device workspace of ws_bytes >= nbody_workspace_bytes(n, 1, variant),
+ *   256-byte aligned; its contents need not be initialised and are scratch.
  * Errors: EINVAL (null pos/mass/acc with n > 0, n < 0, bad eps/G, overlap of
- * acc with pos), ENOTSUP (unknown variant), EWORKSPACE, EHIP. */
+ * acc with pos), ENOTSUP (unknown variant), EWORKSPACE (missing, too small or
+ * misaligned workspace), EHIP. */
 nbody_status nbody_accel(const double *pos, const double *mass, int64_t n,
                          double eps, double G, int32_t variant,
                          double *acc, double *pot,

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <cstdint>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -48,9 +49,9 @@ WsLayout ws_layout(int64_t n, int32_t variant) {
   const size_t jw = variant == NBODY_FP32_COMP ? 2 : 1;
   size_t off = 0;
   L.packed = off;
-  off += align_up(un * sizeof(float4));
+  off += align_up(static_cast<size_t>(nb::padded(n)) * jw * sizeof(float4));
   L.part = off;
-  off += align_up(static_cast<size_t>(nb::kMaxSplit) * un * jw * sizeof(float4));
+  off += align_up(static_cast<size_t>(nb::max_split(n)) * un * jw * sizeof(float4));
   L.pot = off;
   off += align_up(un * sizeof(double));
   L.diag = off;
@@ -95,18 +96,23 @@ int size_class(int64_t n) {
   return c;
 }
 
+// Built-in table, measured on MI355X by paper_2509_19294_amd.autotune
+// (Plummer spheres of 2^c particles, eps = 0.01): {cfg, split} per size class
+// 10..20 for the plain and compensated forms; smaller classes take class 10's
+// entry and larger ones class 20's. Batched modes for classes 8..13.
+const SingleTune kTuned[2][11] = {
+    {{5, 4}, {5, 8}, {4, 4}, {4, 8}, {5, 16}, {4, 16}, {14, 32}, {14, 32}, {14, 32}, {14, 2}, {14, 2}},
+    {{5, 4}, {5, 8}, {5, 8}, {0, 16}, {15, 16}, {9, 32}, {9, 32}, {9, 32}, {9, 32}, {15, 2}, {9, 2}},
+};
+const int kTunedBatched[2][6] = {{1, 1, 1, 1, 1, 1}, {0, 0, 2, 2, 2, 0}};
+
 void tune_defaults() {
   for (int v = 0; v < 2; ++v) {
     for (int c = 0; c < kClasses; ++c) {
-      // Default: two i per thread, 256-wide tiles, enough grid j-split to put
-      // about 1024 blocks on the device for mid-size systems.
-      g_single[v][c] = SingleTune{1, 1};
-      const int64_t n = int64_t{1} << c;
-      const int64_t blocks = (n + 511) / 512;
-      int split = 1;
-      while (split < nb::kMaxSplit && blocks * split < 1024 && n / (split * 2) >= 2048) split *= 2;
-      g_single[v][c].split = split;
-      g_batched[v][c] = c < 10 ? 0 : (c < 11 ? 1 : 2);
+      const int tc = c < 10 ? 0 : (c > 20 ? 10 : c - 10);
+      g_single[v][c] = kTuned[v][tc];
+      const int bc = c < 8 ? 0 : (c > 13 ? 5 : c - 8);
+      g_batched[v][c] = kTunedBatched[v][bc];
       g_forced[v][c] = -1;
     }
   }
@@ -233,6 +239,7 @@ nbody_status check_scalars(double eps, double G) {
 nbody_status check_ws(void *ws, size_t ws_bytes, int64_t n, int32_t variant) {
   const size_t need = ws_layout(n, variant).total;
   if (!ws) return fail(NBODY_EWORKSPACE, "workspace is NULL (need %zu bytes)", need);
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(NBODY_EWORKSPACE, "workspace must be 256-byte aligned");
   if (ws_bytes < need) return fail(NBODY_EWORKSPACE, "workspace of %zu bytes < %zu required", ws_bytes, need);
   return NBODY_OK;
 }
@@ -244,8 +251,9 @@ hipError_t enqueue_accel(const double *pos, const double *mass, int64_t n, doubl
   const SingleTune t = single_tune(variant, n);
   const bool comp = variant == NBODY_FP32_COMP;
   float4 *packed = at<float4>(ws, L.packed);
-  if (!comp) {
-    const hipError_t e = nb::launch_pack(pos, mass, n, packed, st);
+  const bool smem = nb::single_cfg(t.cfg).smem != 0;
+  if (!comp || smem) {
+    const hipError_t e = nb::launch_pack(pos, mass, n, packed, st, comp);
     if (e != hipSuccess) return e;
   }
   hipEvent_t stop = timing_begin(st);

@@ -390,25 +390,249 @@ __global__ __launch_bounds__(256) void combine_kernel(const float4 *__restrict__
 
 __global__ __launch_bounds__(256) void pack_kernel(const double *__restrict__ pos,
                                                    const double *__restrict__ mass, int64_t n,
-                                                   float4 *__restrict__ out) {
+                                                   int64_t npad, float4 *__restrict__ out) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (i >= n) return;
+  if (i >= npad) return;
+  if (i >= n) {
+    out[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
   out[i] = make_float4(static_cast<float>(pos[3 * i]), static_cast<float>(pos[3 * i + 1]),
                        static_cast<float>(pos[3 * i + 2]), static_cast<float>(mass[i]));
 }
 
-// Compiled single-system configurations: {block, k, ls, sw, tile}.
+// Double-single pack relative to the frame c = pos[0].
+__global__ __launch_bounds__(256) void pack_ds_kernel(const double *__restrict__ pos,
+                                                      const double *__restrict__ mass, int64_t n,
+                                                      int64_t npad, float4 *__restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= npad) return;
+  if (i >= n) {
+    out[2 * i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    out[2 * i + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  float hx, hy, hz, lx, ly, lz;
+  ds_split(pos[3 * i] - pos[0], hx, lx);
+  ds_split(pos[3 * i + 1] - pos[1], hy, ly);
+  ds_split(pos[3 * i + 2] - pos[2], hz, lz);
+  out[2 * i] = make_float4(hx, hy, hz, static_cast<float>(mass[i]));
+  out[2 * i + 1] = make_float4(lx, ly, lz, 0.f);
+}
+
+// Four consecutive float4 words, 64-byte aligned: one scalar load.
+struct alignas(64) Quad {
+  float4 v[4];
+};
+
+// Scalar-stream form of the pair kernel. The source index is the same for
+// every lane of a wave, so each wave streams its sources straight from the
+// packed array with scalar loads (four float4 words per load); coordinates
+// and masses arrive in SGPRs and enter the VALU as scalar operands. There is
+// no LDS staging and no barrier in the loop, and source operands cost no VGPR
+// reads. The packed array is padded with zero-mass entries to a multiple of
+// 64, and every split boundary is a multiple of 64, so the loop needs no
+// bounds checks. SW waves of a block share an i-group and take interleaved
+// groups of sources; their sums are combined through LDS in wave order.
+template <int K, int SW, int TJ, bool COMP, bool EPS0>
+__global__ __launch_bounds__(256) void pair_smem_kernel(const float4 *__restrict__ packed,
+                                                        const double *__restrict__ mass,
+                                                        int64_t n, float eps2f, int64_t split_len,
+                                                        OutArgs o) {
+  constexpr int NW = 4;
+  constexpr int NG = NW / SW;
+  constexpr int IB = NG * 64 * K;
+  constexpr int JW = COMP ? 2 : 1;
+  constexpr int G = 4;                  // sources per group
+  constexpr int STEP = SW * G;          // stride between a wave's groups
+  static_assert(NW % SW == 0 && TJ % G == 0, "bad shape");
+  __shared__ float X[(SW > 1) ? (SW - 1) * NG * 64 * K * 4 * JW : 1];
+
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  const int wj = wave % SW, wg = wave / SW;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * IB;
+  const int64_t i1 = i0 + IB < n ? i0 + IB : n;
+  const int64_t np = padded(n);
+  const int64_t J0 = static_cast<int64_t>(blockIdx.y) * split_len;
+  const int64_t J1 = J0 + split_len < np ? J0 + split_len : np;
+
+  float xh[K], yh[K], zh[K], xl[K], yl[K], zl[K], mi[K];
+  int64_t iidx[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t i = i0 + static_cast<int64_t>(k) * (NG * 64) + wg * 64 + lane;
+    iidx[k] = i;
+    const int64_t ic = i < i1 ? i : i1 - 1;
+    const float4 P = packed[ic * JW];
+    xh[k] = P.x;
+    yh[k] = P.y;
+    zh[k] = P.z;
+    mi[k] = P.w;
+    if constexpr (COMP) {
+      const float4 L = packed[ic * JW + 1];
+      xl[k] = L.x;
+      yl[k] = L.y;
+      zl[k] = L.z;
+    } else {
+      xl[k] = yl[k] = zl[k] = 0.f;
+    }
+  }
+
+  float ah[K][4], al[K][4];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ah[k][c] = al[k][c] = 0.f;
+
+  const Quad *Qp = reinterpret_cast<const Quad *>(packed);
+  for (int64_t t = J0 + wj * G; t < J1; t += static_cast<int64_t>(TJ) * SW) {
+    const int64_t tend = t + static_cast<int64_t>(TJ) * SW < J1 ? t + static_cast<int64_t>(TJ) * SW : J1;
+    float p[K][4];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) p[k][c] = 0.f;
+    // Waves on a SIMD hide each other's scalar-load latency (the loop keeps
+    // 8 waves per SIMD resident); group counters are 32-bit so the loop
+    // control stays on the scalar unit.
+    const uint32_t ngroups = static_cast<uint32_t>((tend - t + STEP - 1) / STEP);
+    const Quad *Qt = Qp + ((static_cast<uint64_t>(t) * JW) >> 2);
+    for (uint32_t gi = 0; gi < ngroups; ++gi) {
+      const Quad *Qg = Qt + gi * (STEP * JW / 4);
+      float4 H[G], L[G];
+      if constexpr (COMP) {
+        const Quad c0 = Qg[0], c1 = Qg[1];
+        H[0] = c0.v[0]; L[0] = c0.v[1]; H[1] = c0.v[2]; L[1] = c0.v[3];
+        H[2] = c1.v[0]; L[2] = c1.v[1]; H[3] = c1.v[2]; L[3] = c1.v[3];
+      } else {
+        const Quad c0 = Qg[0];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          H[g] = c0.v[g];
+          L[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          float dx, dy, dz;
+          if constexpr (COMP) {
+            dx = (H[g].x - xh[k]) + (L[g].x - xl[k]);
+            dy = (H[g].y - yh[k]) + (L[g].y - yl[k]);
+            dz = (H[g].z - zh[k]) + (L[g].z - zl[k]);
+          } else {
+            dx = H[g].x - xh[k];
+            dy = H[g].y - yh[k];
+            dz = H[g].z - zh[k];
+          }
+          float r2 = fmaf(dx, dx, eps2f);
+          r2 = fmaf(dy, dy, r2);
+          r2 = fmaf(dz, dz, r2);
+          float rho = rsq(r2);
+          if constexpr (EPS0) rho = r2 > 0.f ? rho : 0.f;
+          const float mr = H[g].w * rho;
+          const float s = mr * (rho * rho);
+          p[k][0] = fmaf(s, dx, p[k][0]);
+          p[k][1] = fmaf(s, dy, p[k][1]);
+          p[k][2] = fmaf(s, dz, p[k][2]);
+          p[k][3] += mr;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if constexpr (COMP) {
+          float s, e;
+          two_sum(ah[k][c], p[k][c], s, e);
+          ah[k][c] = s;
+          al[k][c] += e;
+        } else {
+          ah[k][c] += p[k][c];
+        }
+      }
+  }
+
+  if constexpr (SW > 1) {
+    constexpr int SLOT = NG * 64 * K * 4 * JW;
+    const int base = (wg * 64 + lane) * K * 4 * JW;
+    if (wj > 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          X[(wj - 1) * SLOT + base + (k * 4 + c) * JW] = ah[k][c];
+          if constexpr (COMP) X[(wj - 1) * SLOT + base + (k * 4 + c) * JW + 1] = al[k][c];
+        }
+    }
+    __syncthreads();
+    if (wj == 0) {
+      for (int w = 1; w < SW; ++w) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const float oh = X[(w - 1) * SLOT + base + (k * 4 + c) * JW];
+            if constexpr (COMP) {
+              const float ol = X[(w - 1) * SLOT + base + (k * 4 + c) * JW + 1];
+              float s, e;
+              two_sum(ah[k][c], oh, s, e);
+              ah[k][c] = s;
+              al[k][c] = (al[k][c] + ol) + e;
+            } else {
+              ah[k][c] += oh;
+            }
+          }
+      }
+    }
+  }
+  if (wj != 0) return;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t i = iidx[k];
+    if (i >= i1) continue;
+    if (o.part) {
+      float4 *P = o.part + (static_cast<int64_t>(blockIdx.y) * o.n + i) * JW;
+      P[0] = make_float4(ah[k][0], ah[k][1], ah[k][2], ah[k][3]);
+      if constexpr (COMP) P[1] = make_float4(al[k][0], al[k][1], al[k][2], al[k][3]);
+    } else {
+      double sum[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        sum[c] = COMP ? static_cast<double>(ah[k][c]) + static_cast<double>(al[k][c])
+                      : static_cast<double>(ah[k][c]);
+      o.acc[3 * i] = o.G * sum[0];
+      o.acc[3 * i + 1] = o.G * sum[1];
+      o.acc[3 * i + 2] = o.G * sum[2];
+      if (o.pot) {
+        const double self = EPS0 ? 0.0 : static_cast<double>(self_term(mi[k], eps2f));
+        o.pot[i] = -o.G * (sum[3] - self);
+      }
+    }
+  }
+}
+
+// Compiled single-system configurations: {block, k, ls, sw, tile, smem}.
 static const PairCfg kSingle[] = {
-    {256, 1, 1, 1, 256},   // 0
-    {256, 2, 1, 1, 256},   // 1
-    {256, 4, 1, 1, 256},   // 2
-    {256, 2, 1, 2, 512},   // 3
-    {256, 1, 1, 4, 1024},  // 4
-    {256, 1, 4, 1, 256},   // 5
-    {256, 4, 1, 2, 512},   // 6
-    {256, 2, 1, 4, 1024},  // 7
-    {256, 8, 1, 1, 256},   // 8
-    {256, 2, 2, 1, 512},   // 9
+    {256, 1, 1, 1, 256, 0},   // 0
+    {256, 2, 1, 1, 256, 0},   // 1
+    {256, 4, 1, 1, 256, 0},   // 2
+    {256, 2, 1, 2, 512, 0},   // 3
+    {256, 1, 1, 4, 1024, 0},  // 4
+    {256, 1, 4, 1, 256, 0},   // 5
+    {256, 4, 1, 2, 512, 0},   // 6
+    {256, 2, 1, 4, 1024, 0},  // 7
+    {256, 8, 1, 1, 256, 0},   // 8
+    {256, 2, 2, 1, 512, 0},   // 9
+    {256, 1, 1, 1, 256, 1},   // 10
+    {256, 2, 1, 1, 256, 1},   // 11
+    {256, 4, 1, 1, 256, 1},   // 12
+    {256, 1, 1, 2, 256, 1},   // 13
+    {256, 2, 1, 2, 256, 1},   // 14
+    {256, 1, 1, 4, 256, 1},   // 15
 };
 int single_cfg_count() { return static_cast<int>(sizeof(kSingle) / sizeof(kSingle[0])); }
 const PairCfg &single_cfg(int idx) { return kSingle[idx]; }
@@ -436,11 +660,33 @@ static hipError_t launch_single_t(bool comp, bool eps0, dim3 grid, const double 
   return hipGetLastError();
 }
 
+template <int K, int SW, int TJ>
+static hipError_t launch_smem_t(bool comp, bool eps0, dim3 grid, const double *mass,
+                                const float4 *packed, int64_t n, float eps2f, int64_t split_len,
+                                const OutArgs &o, hipStream_t st) {
+  if (comp) {
+    if (eps0)
+      pair_smem_kernel<K, SW, TJ, true, true><<<grid, 256, 0, st>>>(packed, mass, n, eps2f, split_len, o);
+    else
+      pair_smem_kernel<K, SW, TJ, true, false><<<grid, 256, 0, st>>>(packed, mass, n, eps2f, split_len, o);
+  } else {
+    if (eps0)
+      pair_smem_kernel<K, SW, TJ, false, true><<<grid, 256, 0, st>>>(packed, mass, n, eps2f, split_len, o);
+    else
+      pair_smem_kernel<K, SW, TJ, false, false><<<grid, 256, 0, st>>>(packed, mass, n, eps2f, split_len, o);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_pack(const double *pos, const double *mass, int64_t n, float4 *packed,
-                       hipStream_t stream) {
+                       hipStream_t stream, bool ds) {
   if (n <= 0) return hipSuccess;
-  const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
-  pack_kernel<<<blocks, 256, 0, stream>>>(pos, mass, n, packed);
+  const int64_t np = padded(n);
+  const unsigned blocks = static_cast<unsigned>((np + 255) / 256);
+  if (ds)
+    pack_ds_kernel<<<blocks, 256, 0, stream>>>(pos, mass, n, np, packed);
+  else
+    pack_kernel<<<blocks, 256, 0, stream>>>(pos, mass, n, np, packed);
   return hipGetLastError();
 }
 
@@ -448,13 +694,17 @@ hipError_t launch_pair_single(int cfg, bool comp, const double *pos, const doubl
                               const float4 *packed, int64_t n, double eps, double G, int split,
                               double *acc, double *pot, float4 *part, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
+  if (cfg < 0 || cfg >= single_cfg_count()) return hipErrorInvalidValue;
   const PairCfg &c = kSingle[cfg];
   const int64_t ib = cfg_iblock(c);
   const int64_t nblk = (n + ib - 1) / ib;
   if (split < 1) split = 1;
-  // Each split covers a whole number of tiles.
+  if (split > max_split(n)) split = max_split(n);
+  // Each split covers a whole number of tiles (and of kPad for the scalar
+  // stream, whose padded source array ends at padded(n)).
+  const int64_t unit = c.smem ? kPad : c.tile;
   int64_t split_len = (n + split - 1) / split;
-  split_len = (split_len + c.tile - 1) / c.tile * c.tile;
+  split_len = (split_len + unit - 1) / unit * unit;
   const float eps2f = static_cast<float>(eps * eps);
   const bool eps0 = eps == 0.0;
   OutArgs o{};
@@ -471,6 +721,8 @@ hipError_t launch_pair_single(int cfg, bool comp, const double *pos, const doubl
   switch (cfg) {
 #define NB_CASE(I, B, K, LS, SW, T) \
   case I: e = launch_single_t<B, K, LS, SW, T>(comp, eps0, grid, pos, mass, packed, n, eps2f, split, split_len, o, stream); break;
+#define NB_SMEM(I, K, SW, T) \
+  case I: e = launch_smem_t<K, SW, T>(comp, eps0, grid, mass, packed, n, eps2f, split_len, o, stream); break;
     NB_CASE(0, 256, 1, 1, 1, 256)
     NB_CASE(1, 256, 2, 1, 1, 256)
     NB_CASE(2, 256, 4, 1, 1, 256)
@@ -481,7 +733,14 @@ hipError_t launch_pair_single(int cfg, bool comp, const double *pos, const doubl
     NB_CASE(7, 256, 2, 1, 4, 1024)
     NB_CASE(8, 256, 8, 1, 1, 256)
     NB_CASE(9, 256, 2, 2, 1, 512)
+    NB_SMEM(10, 1, 1, 256)
+    NB_SMEM(11, 2, 1, 256)
+    NB_SMEM(12, 4, 1, 256)
+    NB_SMEM(13, 1, 2, 256)
+    NB_SMEM(14, 2, 2, 256)
+    NB_SMEM(15, 1, 4, 256)
 #undef NB_CASE
+#undef NB_SMEM
     default:
       return hipErrorInvalidValue;
   }
@@ -559,7 +818,7 @@ hipError_t launch_pair_batched(bool comp, const double *pos, const double *mass,
     pair_batched_kernel<true><<<grid, 256, 0, stream>>>(pos, mass, nullptr, items, n_items, eps_k,
                                                         G, counters, acc, pot);
   } else {
-    e = launch_pack(pos, mass, n_total, packed, stream);
+    e = launch_pack(pos, mass, n_total, packed, stream, false);
     if (e != hipSuccess) return e;
     pair_batched_kernel<false><<<grid, 256, 0, stream>>>(pos, mass, packed, items, n_items, eps_k,
                                                          G, counters, acc, pot);

@@ -9,7 +9,9 @@
 namespace nb {
 
 constexpr int kDiagLen = 16;
-constexpr int kMaxSplit = 8;          // largest grid-level j-split
+constexpr int kMaxSplit = 32;         // largest grid-level j-split
+constexpr int64_t kPartCap = int64_t{1} << 23;  // most split partial entries kept
+constexpr int kPad = 64;              // packed arrays are padded to a multiple of this
 constexpr int kDiagBlocks = 512;      // blocks of the first diagnostics pass
 constexpr int kDiagThreads = 256;
 
@@ -19,8 +21,18 @@ struct PairCfg {
   int k;      // i-particles per thread (register blocking)
   int ls;     // lanes sharing one i (intra-wave j-split, combined by shuffles)
   int sw;     // waves sharing one i-group (inter-wave j-split, combined in LDS)
-  int tile;   // j-particles staged in LDS per tile
+  int tile;   // j-particles per tile (LDS-staged, or per wave for the scalar stream)
+  int smem;   // 0: j-tiles staged in LDS; 1: j streamed by scalar loads into SGPRs
 };
+
+// Largest grid j-split the workspace holds for n particles.
+inline int max_split(int64_t n) {
+  if (n <= 0) return 1;
+  int64_t s = kPartCap / n;
+  if (s > kMaxSplit) s = kMaxSplit;
+  return s < 1 ? 1 : static_cast<int>(s);
+}
+__host__ __device__ inline int64_t padded(int64_t n) { return (n + kPad - 1) / kPad * kPad; }
 
 // i-particles one block covers for an item.
 inline int cfg_iblock(const PairCfg &c) { return (c.block / 64 / c.sw) * (64 / c.ls) * c.k; }
@@ -42,8 +54,12 @@ struct Item {
 };
 
 // Launchers. All enqueue on `stream` and return the launch status.
+// Plain pack: packed[j] = {x, y, z, m} in FP32 for j < n, zeros up to
+// padded(n). Compensated pack (ds = true): packed[2j] = {hi(x-c), hi(y-c),
+// hi(z-c), m}, packed[2j+1] = {lo(x-c), lo(y-c), lo(z-c), 0} with the frame
+// c = pos[0], zeros up to padded(n).
 hipError_t launch_pack(const double *pos, const double *mass, int64_t n, float4 *packed,
-                       hipStream_t stream);
+                       hipStream_t stream, bool ds = false);
 
 // Single system: accelerations (and potentials) of all n particles.
 // `part` must hold split * n * (comp ? 2 : 1) float4 when split > 1.

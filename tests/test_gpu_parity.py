@@ -119,6 +119,24 @@ def test_every_config_matches_oracle_and_is_deterministic(variant, n):
         assert orc.rel_rms(r, results[0]) < 2e-6
 
 
+def test_every_config_compensated_survives_translation():
+    """Every compiled configuration of the compensated form keeps the
+    tolerance on a sphere shifted by 10^3 (each form's frame handling)."""
+    n = 3001
+    pos, _, mass = ics.plummer(n, seed=78)
+    ref_a, ref_p = orc.accel_pot(pos, mass, 0.01)
+    shifted = pos + np.array([-1000.0, 700.0, 1000.0])
+    cls = int(math.floor(math.log2(n)))
+    try:
+        for cfg in range(len(nbody.tune_configs("comp"))):
+            for split in (1, 4):
+                nbody.tune_set("comp", cls, cfg, split)
+                a, p = gpu_accel(shifted, mass, 0.01, "comp")
+                check(a, p, ref_a, ref_p, what=("shifted", cfg, split))
+    finally:
+        nbody.tune_set("comp", cls, -1)
+
+
 def test_permutation_moves_rows_exactly():
     n = 2048
     pos, _, mass = ics.plummer(n, seed=3)
