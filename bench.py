@@ -34,6 +34,14 @@ FLOPS_PER_INTERACTION = 20        # the conventional count for one softened pair
 DEFAULT_VARIANT = {"plummer_1k": "plain", "plummer_64k": "plain", "plummer_256k": "comp",
                    "kroupa_1m": "comp", "ensemble_512": "comp"}
 
+# HBM bytes per force-kernel launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# passes, scaled by a 1 GiB copy (fetch x2.000, write x1.000), for the tuned
+# dispatch they were taken on: (workload, variant, cfg, split) -> bytes. A run
+# whose dispatch differs reports null.
+MEASURED_TRAFFIC = {
+    ("plummer_64k", "plain", 14, 32): 49328074,
+}
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -190,6 +198,10 @@ def main():
         launches, kernel_ms = nbody.timing_read()
         nbody.timing_enable(False)
 
+    traffic = None
+    if plan is None:
+        cfg, split = nbody.tune_get(variant, n)
+        traffic = MEASURED_TRAFFIC.get((name, variant, cfg, split))
     ms_per_step = ms_total / args.steps
     value = pairs_per_eval / (ms_per_step * 1e-3) / 1e9
     kernel_avg_ms = kernel_ms / max(launches, 1)
@@ -223,7 +235,7 @@ def main():
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-            "traffic": None,
+            "traffic": traffic,
             "kernel_avg_ms": round(kernel_avg_ms, 4),
             "kernel_launches": launches,
             "flops_per_interaction": FLOPS_PER_INTERACTION,

@@ -179,8 +179,8 @@ nbody_status nbody_tune_reset(void);
 /* Kernel timing, for measurement. While enabled (on != 0), every
  * force-kernel launch made outside graph capture by nbody_accel, nbody_step
  * and nbody_accel_batched is bracketed by HIP events recorded on the stream
- * it runs on (the bracket covers the pair kernel and, with a grid j-split, its
- * combine kernel). nbody_timing_read waits for those events, returns the
+ * it runs on (the bracket covers the pair kernel alone, not the pack before it
+ * nor the split combine after it). nbody_timing_read waits for those events, returns the
  * number of bracketed launches and their summed duration in milliseconds, and
  * clears the record. Enabling or disabling also clears it. Not thread-safe:
  * meant for one measuring thread. */

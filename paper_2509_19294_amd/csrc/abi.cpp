@@ -257,10 +257,8 @@ hipError_t enqueue_accel(const double *pos, const double *mass, int64_t n, doubl
     if (e != hipSuccess) return e;
   }
   hipEvent_t stop = timing_begin(st);
-  const hipError_t e = nb::launch_pair_single(t.cfg, comp, pos, mass, packed, n, eps, G, t.split,
-                                              acc, pot, at<float4>(ws, L.part), st);
-  timing_end(stop, st);
-  return e;
+  return nb::launch_pair_single(t.cfg, comp, pos, mass, packed, n, eps, G, t.split, acc, pot,
+                                at<float4>(ws, L.part), st, stop);
 }
 
 }  // namespace

@@ -692,7 +692,8 @@ hipError_t launch_pack(const double *pos, const double *mass, int64_t n, float4 
 
 hipError_t launch_pair_single(int cfg, bool comp, const double *pos, const double *mass,
                               const float4 *packed, int64_t n, double eps, double G, int split,
-                              double *acc, double *pot, float4 *part, hipStream_t stream) {
+                              double *acc, double *pot, float4 *part, hipStream_t stream,
+                              hipEvent_t after_pair) {
   if (n <= 0) return hipSuccess;
   if (cfg < 0 || cfg >= single_cfg_count()) return hipErrorInvalidValue;
   const PairCfg &c = kSingle[cfg];
@@ -744,6 +745,7 @@ hipError_t launch_pair_single(int cfg, bool comp, const double *pos, const doubl
     default:
       return hipErrorInvalidValue;
   }
+  if (e == hipSuccess && after_pair) e = hipEventRecord(after_pair, stream);
   if (e != hipSuccess || split == 1) return e;
   const unsigned cb = static_cast<unsigned>((n + 255) / 256);
   if (comp)

@@ -62,10 +62,13 @@ hipError_t launch_pack(const double *pos, const double *mass, int64_t n, float4 
                        hipStream_t stream, bool ds = false);
 
 // Single system: accelerations (and potentials) of all n particles.
-// `part` must hold split * n * (comp ? 2 : 1) float4 when split > 1.
+// `part` must hold split * n * (comp ? 2 : 1) float4 when split > 1. If
+// `after_pair` is non-null it is recorded right after the pair kernel (before
+// the split combine), for measurement.
 hipError_t launch_pair_single(int cfg, bool comp, const double *pos, const double *mass,
                               const float4 *packed, int64_t n, double eps, double G, int split,
-                              double *acc, double *pot, float4 *part, hipStream_t stream);
+                              double *acc, double *pot, float4 *part, hipStream_t stream,
+                              hipEvent_t after_pair = nullptr);
 
 // Batched persistent kernel over a work list.
 // `packed` (n_total float4) is scratch for the plain form; `counters` holds
