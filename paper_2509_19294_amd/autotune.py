@@ -132,6 +132,7 @@ def main():
     ap.add_argument("--max-log2", type=int, default=20)
     ap.add_argument("--variants", default="plain,comp")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-single", action="store_true")
     args = ap.parse_args()
     nbody.load()
     nbody.tune_reset()
@@ -144,7 +145,7 @@ def main():
 
     for variant in args.variants.split(","):
         v = nbody.VARIANTS[variant]
-        for c in range(args.min_log2, args.max_log2 + 1):
+        for c in ([] if args.no_single else range(args.min_log2, args.max_log2 + 1)):
             (cfg, sp, ms), _ = tune_single(variant, c, log=log)
             lines.append(f"single {v} {c} {cfg} {sp}")
             print(f"# best {variant} 2^{c}: cfg {cfg} split {sp} {ms:.4f} ms", flush=True)

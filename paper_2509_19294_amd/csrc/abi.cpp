@@ -43,13 +43,22 @@ struct WsLayout {
   size_t packed, part, pot, diag, ctr, total;
 };
 
-WsLayout ws_layout(int64_t n, int32_t variant) {
+// Packed sources: padded(n) entries for a single system; a batched plan's
+// slot layout pads every cluster to a multiple of kSlotAlign.
+int64_t packed_entries(int64_t n, int32_t n_clusters) {
+  const int64_t single = nb::padded(n);
+  if (n_clusters <= 1) return single;
+  const int64_t slots = nb::padded(n + static_cast<int64_t>(nb::kSlotAlign) * n_clusters);
+  return slots > single ? slots : single;
+}
+
+WsLayout ws_layout(int64_t n, int32_t variant, int32_t n_clusters = 1) {
   WsLayout L{};
   const size_t un = static_cast<size_t>(n);
   const size_t jw = variant == NBODY_FP32_COMP ? 2 : 1;
   size_t off = 0;
   L.packed = off;
-  off += align_up(static_cast<size_t>(nb::padded(n)) * jw * sizeof(float4));
+  off += align_up(static_cast<size_t>(packed_entries(n, n_clusters)) * jw * sizeof(float4));
   L.part = off;
   off += align_up(static_cast<size_t>(nb::max_split(n)) * un * jw * sizeof(float4));
   L.pot = off;
@@ -104,7 +113,7 @@ const SingleTune kTuned[2][11] = {
     {{5, 4}, {5, 8}, {4, 4}, {4, 8}, {5, 16}, {4, 16}, {14, 32}, {14, 32}, {14, 32}, {14, 2}, {14, 2}},
     {{5, 4}, {5, 8}, {5, 8}, {0, 16}, {15, 16}, {9, 32}, {9, 32}, {9, 32}, {9, 32}, {15, 2}, {9, 2}},
 };
-const int kTunedBatched[2][6] = {{1, 1, 1, 1, 1, 1}, {0, 0, 2, 2, 2, 0}};
+const int kTunedBatched[2][6] = {{8, 4, 4, 4, 4, 4}, {1, 4, 4, 4, 4, 4}};
 
 void tune_defaults() {
   for (int v = 0; v < 2; ++v) {
@@ -236,8 +245,9 @@ nbody_status check_scalars(double eps, double G) {
   return NBODY_OK;
 }
 
-nbody_status check_ws(void *ws, size_t ws_bytes, int64_t n, int32_t variant) {
-  const size_t need = ws_layout(n, variant).total;
+nbody_status check_ws(void *ws, size_t ws_bytes, int64_t n, int32_t variant,
+                      int32_t n_clusters = 1) {
+  const size_t need = ws_layout(n, variant, n_clusters).total;
   if (!ws) return fail(NBODY_EWORKSPACE, "workspace is NULL (need %zu bytes)", need);
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(NBODY_EWORKSPACE, "workspace must be 256-byte aligned");
   if (ws_bytes < need) return fail(NBODY_EWORKSPACE, "workspace of %zu bytes < %zu required", ws_bytes, need);
@@ -276,7 +286,13 @@ struct nbody_plan {
   double pairs = 0.0;
   nb::Item *d_items = nullptr;
   double *d_eps = nullptr;
-  int grid = 0;
+  int32_t *d_slot_src = nullptr;    // slot layout of the packed sources
+  int32_t *d_slot_frame = nullptr;
+  int64_t n_slots = 0;
+  bool need_pack = false;
+  int32_t seg_begin[nb::kBatchedModes] = {};
+  int32_t seg_end[nb::kBatchedModes] = {};
+  int grid[nb::kBatchedModes] = {};
   int device = 0;
   hipStream_t capture = nullptr;
   // Cached graph of one KDK step and the arguments it was captured with.
@@ -289,11 +305,24 @@ namespace {
 
 hipError_t enqueue_batched(const double *pos, const double *mass, nbody_plan *p, double G,
                            double *acc, double *pot, void *ws, hipStream_t st) {
-  const WsLayout L = ws_layout(p->n_total, p->variant);
+  const WsLayout L = ws_layout(p->n_total, p->variant, p->K);
+  nb::BatchedArgs b{};
+  b.items = p->d_items;
+  b.n_items = p->n_items;
+  b.eps_k = p->d_eps;
+  b.slot_src = p->d_slot_src;
+  b.slot_frame = p->d_slot_frame;
+  b.n_slots = p->n_slots;
+  for (int m = 0; m < nb::kBatchedModes; ++m) {
+    b.seg_begin[m] = p->seg_begin[m];
+    b.seg_end[m] = p->seg_end[m];
+    b.grid[m] = p->grid[m];
+  }
+  b.comp = p->variant == NBODY_FP32_COMP;
+  b.need_pack = p->need_pack;
   hipEvent_t stop = timing_begin(st);
-  const hipError_t e = nb::launch_pair_batched(
-      p->variant == NBODY_FP32_COMP, pos, mass, at<float4>(ws, L.packed), p->n_total, p->d_items,
-      p->n_items, p->d_eps, G, p->grid, at<int>(ws, L.ctr) + 4, acc, pot, st);
+  const hipError_t e = nb::launch_pair_batched(b, pos, mass, at<float4>(ws, L.packed), G,
+                                               at<int>(ws, L.ctr) + 4, acc, pot, st);
   timing_end(stop, st);
   return e;
 }
@@ -302,7 +331,7 @@ hipError_t enqueue_batched(const double *pos, const double *mass, nbody_plan *p,
 hipError_t enqueue_step(double *pos, double *vel, double *acc, double *pot, const double *mass,
                         int64_t n, double eps, double G, double dt, int32_t variant,
                         nbody_plan *plan, double *diag, void *ws, hipStream_t st) {
-  const WsLayout L = ws_layout(n, variant);
+  const WsLayout L = ws_layout(n, variant, plan ? plan->K : 1);
   const double h = 0.5 * dt;
   hipError_t e = nb::launch_kick_drift(pos, vel, acc, n, h, dt, st);
   if (e != hipSuccess) return e;
@@ -330,7 +359,7 @@ const char *nbody_version(void) { return "nbody-mi355x 0.1 (gfx950)"; }
 
 size_t nbody_workspace_bytes(int64_t n_total, int32_t n_clusters, int32_t variant) {
   if (n_total < 0 || n_clusters < 1 || !valid_variant(variant)) return 0;
-  return ws_layout(n_total, variant).total;
+  return ws_layout(n_total, variant, n_clusters).total;
 }
 
 nbody_status nbody_accel(const double *pos, const double *mass, int64_t n, double eps, double G,
@@ -384,7 +413,7 @@ nbody_plan *nbody_plan_create(const int64_t *offsets_host, int32_t K, const doub
       return nullptr;
     }
   }
-  if (offsets_host[K] >= (int64_t{1} << 31)) {
+  if (offsets_host[K] + static_cast<int64_t>(nb::kSlotAlign) * K >= (int64_t{1} << 31)) {
     fail(NBODY_ENOTSUP, "batched plans hold fewer than 2^31 particles");
     return nullptr;
   }
@@ -401,13 +430,32 @@ nbody_plan *nbody_plan_create(const int64_t *offsets_host, int32_t K, const doub
   p->eps.assign(eps_host, eps_host + K);
   p->n_total = offsets_host[K];
 
+  // Slot layout: cluster k's sources start at a multiple of kSlotAlign and
+  // are followed by zero-mass padding up to the next multiple.
+  std::vector<int64_t> poff(static_cast<size_t>(K) + 1, 0);
+  for (int32_t k = 0; k < K; ++k) {
+    const int64_t nk = p->offsets[k + 1] - p->offsets[k];
+    poff[k + 1] = poff[k] + (nk + nb::kSlotAlign - 1) / nb::kSlotAlign * nb::kSlotAlign;
+  }
+  p->n_slots = poff[K];
+  std::vector<int32_t> slot_src(static_cast<size_t>(p->n_slots), -1), slot_frame(static_cast<size_t>(p->n_slots), 0);
+  for (int32_t k = 0; k < K; ++k) {
+    const int64_t s = p->offsets[k], nk = p->offsets[k + 1] - s;
+    for (int64_t t = 0; t < poff[k + 1] - poff[k]; ++t) {
+      slot_src[poff[k] + t] = t < nk ? static_cast<int32_t>(s + t) : -1;
+      slot_frame[poff[k] + t] = static_cast<int32_t>(nk > 0 ? s : 0);
+    }
+  }
+
   // Work items: every cluster cut into i-blocks of its mode's width; then
   // heaviest first (longest-processing-time order), ties by position.
   std::vector<nb::Item> items;
+  p->need_pack = variant == NBODY_FP32_PLAIN;
   for (int32_t k = 0; k < K; ++k) {
     const int64_t s = p->offsets[k], e = p->offsets[k + 1], nk = e - s;
     if (nk == 0) continue;
     const int mode = batched_tune(variant, nk);
+    if (nb::batched_mode(mode).smem) p->need_pack = true;
     const int ib = nb::cfg_iblock(nb::batched_mode(mode));
     for (int64_t i = s; i < e; i += ib) {
       nb::Item it{};
@@ -417,30 +465,49 @@ nbody_plan *nbody_plan_create(const int64_t *offsets_host, int32_t K, const doub
       it.j1 = static_cast<int32_t>(e);
       it.cluster = k;
       it.mode = mode;
+      it.delta = static_cast<int32_t>(poff[k] - s);
       items.push_back(it);
       p->pairs += static_cast<double>(it.i1 - it.i0) * static_cast<double>(nk);
     }
   }
+  // Grouped by mode (one persistent launch each), heaviest first within a
+  // mode; the stable sort keeps ties in position order.
   std::stable_sort(items.begin(), items.end(), [](const nb::Item &a, const nb::Item &b) {
+    if (a.mode != b.mode) return a.mode < b.mode;
     const int64_t ca = int64_t{a.i1 - a.i0} * (a.j1 - a.j0);
     const int64_t cb = int64_t{b.i1 - b.i0} * (b.j1 - b.j0);
     return ca > cb;
   });
   p->n_items = static_cast<int32_t>(items.size());
+  for (int32_t t = 0; t < p->n_items; ++t) {
+    const int m = items[t].mode;
+    if (p->seg_end[m] == p->seg_begin[m]) p->seg_begin[m] = t;
+    p->seg_end[m] = t + 1;
+  }
 
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess && !items.empty()) e = hipMalloc(&p->d_items, items.size() * sizeof(nb::Item));
   if (e == hipSuccess && !items.empty())
     e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(nb::Item), hipMemcpyHostToDevice);
+  if (e == hipSuccess && p->n_slots > 0) e = hipMalloc(&p->d_slot_src, slot_src.size() * sizeof(int32_t));
+  if (e == hipSuccess && p->n_slots > 0)
+    e = hipMemcpy(p->d_slot_src, slot_src.data(), slot_src.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && p->n_slots > 0) e = hipMalloc(&p->d_slot_frame, slot_frame.size() * sizeof(int32_t));
+  if (e == hipSuccess && p->n_slots > 0)
+    e = hipMemcpy(p->d_slot_frame, slot_frame.data(), slot_frame.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&p->d_eps, static_cast<size_t>(K) * sizeof(double));
   if (e == hipSuccess)
     e = hipMemcpy(p->d_eps, p->eps.data(), static_cast<size_t>(K) * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
-  if (e == hipSuccess) {
-    p->grid = nb::batched_grid(variant == NBODY_FP32_COMP);
-    if (p->grid <= 0) e = hipErrorInvalidDeviceFunction;
-    if (p->grid > p->n_items && p->n_items > 0) p->grid = p->n_items;
-    if (p->grid < 1) p->grid = 1;
+  for (int m = 0; m < nb::kBatchedModes && e == hipSuccess; ++m) {
+    const int32_t cnt = p->seg_end[m] - p->seg_begin[m];
+    if (cnt <= 0) continue;
+    int g = nb::batched_grid(variant == NBODY_FP32_COMP, m);
+    if (g <= 0) {
+      e = hipErrorInvalidDeviceFunction;
+      break;
+    }
+    p->grid[m] = g > cnt ? cnt : g;
   }
   if (e != hipSuccess) {
     hip_fail(e, "nbody_plan_create");
@@ -456,6 +523,8 @@ void nbody_plan_destroy(nbody_plan *p) {
   if (p->capture) (void)hipStreamDestroy(p->capture);
   if (p->d_items) (void)hipFree(p->d_items);
   if (p->d_eps) (void)hipFree(p->d_eps);
+  if (p->d_slot_src) (void)hipFree(p->d_slot_src);
+  if (p->d_slot_frame) (void)hipFree(p->d_slot_frame);
   delete p;
 }
 
@@ -478,7 +547,7 @@ nbody_status nbody_accel_batched(const double *pos, const double *mass, nbody_pl
   if (overlap(acc, b3, pos, b3) || overlap(acc, b3, mass, b1) || overlap(pot, b1, pos, b3) ||
       overlap(pot, b1, mass, b1) || overlap(pot, b1, acc, b3))
     return fail(NBODY_EINVAL, "output arrays overlap inputs or each other");
-  nbody_status st = check_ws(ws, ws_bytes, n, plan->variant);
+  nbody_status st = check_ws(ws, ws_bytes, n, plan->variant, plan->K);
   if (st != NBODY_OK) return st;
   const hipError_t e = enqueue_batched(pos, mass, plan, G, acc, pot, ws, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "nbody_accel_batched launch");
@@ -516,10 +585,10 @@ nbody_status nbody_step(double *pos, double *vel, double *acc, double *pot, cons
                overlap(diag, static_cast<size_t>(n_steps) * nb::kDiagLen * sizeof(double), vel, b3) ||
                overlap(diag, static_cast<size_t>(n_steps) * nb::kDiagLen * sizeof(double), acc, b3)))
     return fail(NBODY_EINVAL, "diag overlaps the state arrays");
-  st = check_ws(ws, ws_bytes, n, variant);
+  st = check_ws(ws, ws_bytes, n, variant, plan ? plan->K : 1);
   if (st != NBODY_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const WsLayout L = ws_layout(n, variant);
+  const WsLayout L = ws_layout(n, variant, plan ? plan->K : 1);
   hipError_t e = hipSuccess;
   if (diag) e = nb::launch_fill_int(at<int>(ws, L.ctr), 1, 0, s);
   if (e != hipSuccess) return hip_fail(e, "nbody_step");

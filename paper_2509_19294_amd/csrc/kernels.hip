@@ -434,28 +434,28 @@ struct alignas(64) Quad {
 // 64, and every split boundary is a multiple of 64, so the loop needs no
 // bounds checks. SW waves of a block share an i-group and take interleaved
 // groups of sources; their sums are combined through LDS in wave order.
+// One block (4 waves) computes targets [i0, i1) (packed index of i0 is ip0)
+// against packed sources [J0, J1); J1 - J0 must be a multiple of 4 * SW.
+// `X` is LDS scratch of smem_lds_floats<K, SW, COMP>() floats.
+template <int K, int SW, bool COMP>
+constexpr int smem_lds_floats() {
+  return (SW > 1) ? (SW - 1) * (4 / SW) * 64 * K * 4 * (COMP ? 2 : 1) : 1;
+}
+
 template <int K, int SW, int TJ, bool COMP, bool EPS0>
-__global__ __launch_bounds__(256) void pair_smem_kernel(const float4 *__restrict__ packed,
-                                                        const double *__restrict__ mass,
-                                                        int64_t n, float eps2f, int64_t split_len,
-                                                        OutArgs o) {
+__device__ __forceinline__ void smem_block(const float4 *__restrict__ packed, int64_t i0,
+                                           int64_t i1, int64_t ip0, int64_t J0, int64_t J1,
+                                           float eps2f, float *X, const OutArgs &o) {
   constexpr int NW = 4;
   constexpr int NG = NW / SW;
-  constexpr int IB = NG * 64 * K;
   constexpr int JW = COMP ? 2 : 1;
   constexpr int G = 4;                  // sources per group
   constexpr int STEP = SW * G;          // stride between a wave's groups
   static_assert(NW % SW == 0 && TJ % G == 0, "bad shape");
-  __shared__ float X[(SW > 1) ? (SW - 1) * NG * 64 * K * 4 * JW : 1];
 
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   const int wj = wave % SW, wg = wave / SW;
-  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * IB;
-  const int64_t i1 = i0 + IB < n ? i0 + IB : n;
-  const int64_t np = padded(n);
-  const int64_t J0 = static_cast<int64_t>(blockIdx.y) * split_len;
-  const int64_t J1 = J0 + split_len < np ? J0 + split_len : np;
 
   float xh[K], yh[K], zh[K], xl[K], yl[K], zl[K], mi[K];
   int64_t iidx[K];
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(256) void pair_smem_kernel(const float4 *__restrict
   for (int k = 0; k < K; ++k) {
     const int64_t i = i0 + static_cast<int64_t>(k) * (NG * 64) + wg * 64 + lane;
     iidx[k] = i;
-    const int64_t ic = i < i1 ? i : i1 - 1;
+    const int64_t ic = (i < i1 ? i : i1 - 1) - i0 + ip0;
     const float4 P = packed[ic * JW];
     xh[k] = P.x;
     yh[k] = P.y;
@@ -595,7 +595,7 @@ __global__ __launch_bounds__(256) void pair_smem_kernel(const float4 *__restrict
     const int64_t i = iidx[k];
     if (i >= i1) continue;
     if (o.part) {
-      float4 *P = o.part + (static_cast<int64_t>(blockIdx.y) * o.n + i) * JW;
+      float4 *P = o.part + (static_cast<int64_t>(o.split_index) * o.n + i) * JW;
       P[0] = make_float4(ah[k][0], ah[k][1], ah[k][2], ah[k][3]);
       if constexpr (COMP) P[1] = make_float4(al[k][0], al[k][1], al[k][2], al[k][3]);
     } else {
@@ -613,6 +613,24 @@ __global__ __launch_bounds__(256) void pair_smem_kernel(const float4 *__restrict
       }
     }
   }
+}
+
+template <int K, int SW, int TJ, bool COMP, bool EPS0>
+__global__ __launch_bounds__(256) void pair_smem_kernel(const float4 *__restrict__ packed,
+                                                        const double *__restrict__ mass,
+                                                        int64_t n, float eps2f, int64_t split_len,
+                                                        OutArgs o) {
+  (void)mass;
+  constexpr int IB = (4 / SW) * 64 * K;
+  __shared__ float X[smem_lds_floats<K, SW, COMP>()];
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * IB;
+  const int64_t i1 = i0 + IB < n ? i0 + IB : n;
+  const int64_t np = padded(n);
+  const int64_t J0 = static_cast<int64_t>(blockIdx.y) * split_len;
+  const int64_t J1 = J0 + split_len < np ? J0 + split_len : np;
+  OutArgs oo = o;
+  oo.split_index = blockIdx.y;
+  smem_block<K, SW, TJ, COMP, EPS0>(packed, i0, i1, i0, J0, J1, eps2f, X, oo);
 }
 
 // Compiled single-system configurations: {block, k, ls, sw, tile, smem}.
@@ -759,42 +777,81 @@ hipError_t launch_pair_single(int cfg, bool comp, const double *pos, const doubl
 // Batched: a persistent grid claims (cluster, i-block) work items, heaviest
 // first, from a global counter.
 
+// Modes: LDS-tiled (0-3) and scalar-stream (4-8) block shapes. Each mode's
+// kernel gets the LDS its shape needs: the double-buffered tile for the LDS
+// modes (which also holds their cross-wave combine), the cross-wave combine
+// buffer for the scalar-stream ones.
+constexpr int kBatchedTile[] = {512, 512, 512, 256, 0, 0, 0, 0, 0};
+constexpr int kBatchedK[] = {1, 1, 2, 2, 1, 1, 2, 1, 2};
+constexpr int kBatchedSW[] = {4, 2, 2, 1, 4, 2, 2, 1, 1};
+constexpr int kBatchedSmem[] = {0, 0, 0, 0, 1, 1, 1, 1, 1};
+
+template <int MODE, bool COMP>
+constexpr int batched_lds_float4() {
+  constexpr int tile = kBatchedTile[MODE] * (COMP ? 2 : 1) * 2;
+  constexpr int sw = kBatchedSW[MODE];
+  constexpr int combine = sw > 1 ? ((sw - 1) * (4 / sw) * 64 * kBatchedK[MODE] * 4 * (COMP ? 2 : 1) + 3) / 4 : 1;
+  return tile > combine ? tile : combine;
+}
 static const PairCfg kBatched[] = {
-    {256, 1, 1, 4, 512},  // 0: 64 i per item, j split over 4 waves
-    {256, 1, 1, 2, 512},  // 1: 128 i per item
-    {256, 2, 1, 2, 512},  // 2: 256 i per item
-    {256, 2, 1, 1, 256},  // 3: 512 i per item
+    {256, 1, 1, 4, 512, 0},  // 0: 64 i per item, j split over 4 waves
+    {256, 1, 1, 2, 512, 0},  // 1: 128 i per item
+    {256, 2, 1, 2, 512, 0},  // 2: 256 i per item
+    {256, 2, 1, 1, 256, 0},  // 3: 512 i per item
+    {256, 1, 1, 4, 256, 1},  // 4: 64 i per item, scalar stream, 4-wave j split
+    {256, 1, 1, 2, 256, 1},  // 5: 128 i
+    {256, 2, 1, 2, 256, 1},  // 6: 256 i
+    {256, 1, 1, 1, 256, 1},  // 7: 256 i
+    {256, 2, 1, 1, 256, 1},  // 8: 512 i
 };
 int batched_mode_count() { return static_cast<int>(sizeof(kBatched) / sizeof(kBatched[0])); }
 const PairCfg &batched_mode(int idx) { return kBatched[idx]; }
 
-template <bool COMP, bool EPS0>
-__device__ __forceinline__ void batched_dispatch(int mode, const double *__restrict__ pos,
-                                                 const double *__restrict__ mass,
-                                                 const float4 *__restrict__ packed, int64_t i0,
-                                                 int64_t i1, int64_t j0, int64_t j1, float eps2f,
-                                                 float4 *lds, const OutArgs &o) {
-  switch (mode) {
-    case 0: pair_block<256, 1, 1, 4, 512, COMP, EPS0>(pos, mass, packed, i0, i1, j0, j1, eps2f, lds, o); break;
-    case 1: pair_block<256, 1, 1, 2, 512, COMP, EPS0>(pos, mass, packed, i0, i1, j0, j1, eps2f, lds, o); break;
-    case 2: pair_block<256, 2, 1, 2, 512, COMP, EPS0>(pos, mass, packed, i0, i1, j0, j1, eps2f, lds, o); break;
-    default: pair_block<256, 2, 1, 1, 256, COMP, EPS0>(pos, mass, packed, i0, i1, j0, j1, eps2f, lds, o); break;
-  }
+// Item sources in the slot layout: cluster k's sources start at slot
+// j0 + delta and are zero-padded to a multiple of kSlotAlign.
+template <int MODE, bool COMP, bool EPS0>
+__device__ __forceinline__ void batched_item(const Item &d, const double *__restrict__ pos,
+                                             const double *__restrict__ mass,
+                                             const float4 *__restrict__ packed, float eps2f,
+                                             float4 *lds, const OutArgs &o) {
+  const int64_t i0 = d.i0, i1 = d.i1, j0 = d.j0, j1 = d.j1, delta = d.delta;
+  // LDS modes read the plain sources through a shifted base (slot = j + delta).
+  const float4 *pj = COMP ? nullptr : packed + delta;
+  const int64_t s0 = j0 + delta;
+  const int64_t s1 = s0 + (j1 - j0 + kSlotAlign - 1) / kSlotAlign * kSlotAlign;
+  float *X = reinterpret_cast<float *>(lds);
+  static_assert(kBatchedSmem[MODE] == 0 ||
+                    smem_lds_floats<kBatchedK[MODE], kBatchedSW[MODE], COMP>() <= 4 * batched_lds_float4<MODE, COMP>(),
+                "batched LDS too small for the cross-wave combine");
+  if constexpr (MODE == 0) pair_block<256, 1, 1, 4, 512, COMP, EPS0>(pos, mass, pj, i0, i1, j0, j1, eps2f, lds, o);
+  if constexpr (MODE == 1) pair_block<256, 1, 1, 2, 512, COMP, EPS0>(pos, mass, pj, i0, i1, j0, j1, eps2f, lds, o);
+  if constexpr (MODE == 2) pair_block<256, 2, 1, 2, 512, COMP, EPS0>(pos, mass, pj, i0, i1, j0, j1, eps2f, lds, o);
+  if constexpr (MODE == 3) pair_block<256, 2, 1, 1, 256, COMP, EPS0>(pos, mass, pj, i0, i1, j0, j1, eps2f, lds, o);
+  if constexpr (MODE == 4) smem_block<1, 4, 256, COMP, EPS0>(packed, i0, i1, i0 + delta, s0, s1, eps2f, X, o);
+  if constexpr (MODE == 5) smem_block<1, 2, 256, COMP, EPS0>(packed, i0, i1, i0 + delta, s0, s1, eps2f, X, o);
+  if constexpr (MODE == 6) smem_block<2, 2, 256, COMP, EPS0>(packed, i0, i1, i0 + delta, s0, s1, eps2f, X, o);
+  if constexpr (MODE == 7) smem_block<1, 1, 256, COMP, EPS0>(packed, i0, i1, i0 + delta, s0, s1, eps2f, X, o);
+  if constexpr (MODE == 8) smem_block<2, 1, 256, COMP, EPS0>(packed, i0, i1, i0 + delta, s0, s1, eps2f, X, o);
 }
 
-template <bool COMP>
+
+// One persistent launch per mode: the grid claims the mode's items (a
+// contiguous, heaviest-first segment of the plan's work list) from its own
+// counter until none is left.
+template <int MODE, bool COMP>
 __global__ __launch_bounds__(256) void pair_batched_kernel(
     const double *__restrict__ pos, const double *__restrict__ mass,
-    const float4 *__restrict__ packed, const Item *__restrict__ items, int32_t n_items, const double *__restrict__ eps_k, double G,
-    int *__restrict__ counters, double *__restrict__ acc, double *__restrict__ pot) {
-  __shared__ float4 lds[2 * 512 * 2];
+    const float4 *__restrict__ packed, const Item *__restrict__ items, int32_t n_items,
+    const double *__restrict__ eps_k, double G, int *__restrict__ counter,
+    double *__restrict__ acc, double *__restrict__ pot) {
+  __shared__ float4 lds[batched_lds_float4<MODE, COMP>()];
   __shared__ int s_item;
   OutArgs o{};
   o.acc = acc;
   o.pot = pot;
   o.G = G;
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&counters[0], 1);
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
     const int it = s_item;
     __syncthreads();
@@ -803,40 +860,116 @@ __global__ __launch_bounds__(256) void pair_batched_kernel(
     const double eps = eps_k[d.cluster];
     const float eps2f = static_cast<float>(eps * eps);
     if (eps == 0.0)
-      batched_dispatch<COMP, true>(d.mode, pos, mass, packed, d.i0, d.i1, d.j0, d.j1, eps2f, lds, o);
+      batched_item<MODE, COMP, true>(d, pos, mass, packed, eps2f, lds, o);
     else
-      batched_dispatch<COMP, false>(d.mode, pos, mass, packed, d.i0, d.i1, d.j0, d.j1, eps2f, lds, o);
+      batched_item<MODE, COMP, false>(d, pos, mass, packed, eps2f, lds, o);
     __syncthreads();
   }
 }
 
-hipError_t launch_pair_batched(bool comp, const double *pos, const double *mass,
-                               float4 *packed, int64_t n_total, const Item *items,
-                               int32_t n_items, const double *eps_k, double G, int grid,
-                               int *counters, double *acc, double *pot, hipStream_t stream) {
-  hipError_t e = launch_fill_int(counters, 2, 0, stream);
-  if (e != hipSuccess || n_items == 0) return e;
-  if (comp) {
-    pair_batched_kernel<true><<<grid, 256, 0, stream>>>(pos, mass, nullptr, items, n_items, eps_k,
-                                                        G, counters, acc, pot);
+// Slot-layout pack of a batched plan: slot s holds source slot_src[s] (or
+// zero-mass padding when negative); the compensated form splits x - c with
+// the cluster frame c = pos[slot_frame[s]].
+__global__ __launch_bounds__(256) void pack_slots_kernel(const double *__restrict__ pos,
+                                                         const double *__restrict__ mass,
+                                                         const int32_t *__restrict__ slot_src,
+                                                         const int32_t *__restrict__ slot_frame,
+                                                         int64_t n_slots, int ds,
+                                                         float4 *__restrict__ out) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (s >= n_slots) return;
+  const int64_t j = slot_src[s];
+  if (ds) {
+    if (j < 0) {
+      out[2 * s] = make_float4(0.f, 0.f, 0.f, 0.f);
+      out[2 * s + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+      return;
+    }
+    const int64_t f = slot_frame[s];
+    float hx, hy, hz, lx, ly, lz;
+    ds_split(pos[3 * j] - pos[3 * f], hx, lx);
+    ds_split(pos[3 * j + 1] - pos[3 * f + 1], hy, ly);
+    ds_split(pos[3 * j + 2] - pos[3 * f + 2], hz, lz);
+    out[2 * s] = make_float4(hx, hy, hz, static_cast<float>(mass[j]));
+    out[2 * s + 1] = make_float4(lx, ly, lz, 0.f);
   } else {
-    e = launch_pack(pos, mass, n_total, packed, stream, false);
-    if (e != hipSuccess) return e;
-    pair_batched_kernel<false><<<grid, 256, 0, stream>>>(pos, mass, packed, items, n_items, eps_k,
-                                                         G, counters, acc, pot);
+    out[s] = j < 0 ? make_float4(0.f, 0.f, 0.f, 0.f)
+                   : make_float4(static_cast<float>(pos[3 * j]), static_cast<float>(pos[3 * j + 1]),
+                                 static_cast<float>(pos[3 * j + 2]), static_cast<float>(mass[j]));
   }
+}
+
+template <int MODE>
+static hipError_t launch_mode(const BatchedArgs &b, int m, const double *pos, const double *mass,
+                             const float4 *packed, double G, int *counters, double *acc,
+                             double *pot, hipStream_t st) {
+  const Item *it = b.items + b.seg_begin[m];
+  const int32_t cnt = b.seg_end[m] - b.seg_begin[m];
+  if (b.comp)
+    pair_batched_kernel<MODE, true><<<b.grid[m], 256, 0, st>>>(pos, mass, packed, it, cnt, b.eps_k,
+                                                                G, counters + m, acc, pot);
+  else
+    pair_batched_kernel<MODE, false><<<b.grid[m], 256, 0, st>>>(pos, mass, packed, it, cnt, b.eps_k,
+                                                                 G, counters + m, acc, pot);
   return hipGetLastError();
 }
 
-int batched_grid(bool comp) {
-  int dev = 0, cus = 0, per = 0;
+hipError_t launch_pair_batched(const BatchedArgs &b, const double *pos, const double *mass,
+                               float4 *packed, double G, int *counters, double *acc, double *pot,
+                               hipStream_t stream) {
+  if (b.n_items == 0) return hipSuccess;
+  hipError_t e = launch_fill_int(counters, kBatchedModes, 0, stream);
+  if (e != hipSuccess) return e;
+  if (b.need_pack) {
+    const unsigned blocks = static_cast<unsigned>((b.n_slots + 255) / 256);
+    pack_slots_kernel<<<blocks, 256, 0, stream>>>(pos, mass, b.slot_src, b.slot_frame, b.n_slots,
+                                                  b.comp ? 1 : 0, packed);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  for (int m = 0; m < kBatchedModes && e == hipSuccess; ++m) {
+    if (b.seg_end[m] <= b.seg_begin[m]) continue;
+    switch (m) {
+      case 0: e = launch_mode<0>(b, m, pos, mass, packed, G, counters, acc, pot, stream); break;
+      case 1: e = launch_mode<1>(b, m, pos, mass, packed, G, counters, acc, pot, stream); break;
+      case 2: e = launch_mode<2>(b, m, pos, mass, packed, G, counters, acc, pot, stream); break;
+      case 3: e = launch_mode<3>(b, m, pos, mass, packed, G, counters, acc, pot, stream); break;
+      case 4: e = launch_mode<4>(b, m, pos, mass, packed, G, counters, acc, pot, stream); break;
+      case 5: e = launch_mode<5>(b, m, pos, mass, packed, G, counters, acc, pot, stream); break;
+      case 6: e = launch_mode<6>(b, m, pos, mass, packed, G, counters, acc, pot, stream); break;
+      case 7: e = launch_mode<7>(b, m, pos, mass, packed, G, counters, acc, pot, stream); break;
+      default: e = launch_mode<8>(b, m, pos, mass, packed, G, counters, acc, pot, stream); break;
+    }
+  }
+  return e;
+}
+
+template <int MODE>
+static int occupancy(bool comp) {
+  int per = 0;
+  const hipError_t e =
+      comp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pair_batched_kernel<MODE, true>, 256, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pair_batched_kernel<MODE, false>, 256, 0);
+  return e == hipSuccess ? per : 0;
+}
+
+int batched_grid(bool comp, int mode) {
+  int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  const hipError_t e =
-      comp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pair_batched_kernel<true>, 256, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pair_batched_kernel<false>, 256, 0);
-  if (e != hipSuccess) return 0;
+  int per = 0;
+  switch (mode) {
+    case 0: per = occupancy<0>(comp); break;
+    case 1: per = occupancy<1>(comp); break;
+    case 2: per = occupancy<2>(comp); break;
+    case 3: per = occupancy<3>(comp); break;
+    case 4: per = occupancy<4>(comp); break;
+    case 5: per = occupancy<5>(comp); break;
+    case 6: per = occupancy<6>(comp); break;
+    case 7: per = occupancy<7>(comp); break;
+    default: per = occupancy<8>(comp); break;
+  }
   if (per < 1) per = 1;
   return cus * per;
 }

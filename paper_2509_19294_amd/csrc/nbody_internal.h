@@ -45,12 +45,34 @@ const PairCfg &single_cfg(int idx);
 int batched_mode_count();
 const PairCfg &batched_mode(int idx);
 
-// Work item of the batched kernel: i in [i0, i1) against j in [j0, j1).
+// Work item of the batched kernel: i in [i0, i1) against j in [j0, j1)
+// (particle indices); the cluster's sources sit at slots [j0 + delta, ...) of
+// the plan's slot layout, zero-padded to a multiple of kSlotAlign.
 struct Item {
   int32_t i0, i1, j0, j1;
   int32_t cluster;  // index into the per-cluster eps array
   int32_t mode;     // batched_mode index
-  int32_t pad0, pad1;
+  int32_t delta;    // slot of particle j0 minus j0
+  int32_t pad;
+};
+constexpr int kSlotAlign = 16;
+constexpr int kBatchedModes = 9;
+
+// Device arrays of a batched plan used by one force evaluation. Items are
+// grouped by mode; mode m owns items [seg_begin[m], seg_end[m]) and runs as
+// its own persistent launch of grid[m] blocks.
+struct BatchedArgs {
+  const Item *items;
+  int32_t n_items;
+  int32_t seg_begin[kBatchedModes];
+  int32_t seg_end[kBatchedModes];
+  int grid[kBatchedModes];
+  const double *eps_k;
+  const int32_t *slot_src;    // [n_slots] particle index of a slot, -1 for padding
+  const int32_t *slot_frame;  // [n_slots] particle index of the slot's cluster frame
+  int64_t n_slots;
+  bool comp;
+  bool need_pack;  // plain form, or any scalar-stream mode
 };
 
 // Launchers. All enqueue on `stream` and return the launch status.
@@ -70,14 +92,13 @@ hipError_t launch_pair_single(int cfg, bool comp, const double *pos, const doubl
                               double *acc, double *pot, float4 *part, hipStream_t stream,
                               hipEvent_t after_pair = nullptr);
 
-// Batched persistent kernel over a work list.
-// `packed` (n_total float4) is scratch for the plain form; `counters` holds
-// two ints (work counter, reserved) reset by a fill kernel before the launch.
-hipError_t launch_pair_batched(bool comp, const double *pos, const double *mass,
-                               float4 *packed, int64_t n_total, const Item *items,
-                               int32_t n_items, const double *eps_k, double G, int grid,
-                               int *counters, double *acc, double *pot, hipStream_t stream);
-int batched_grid(bool comp);  // persistent grid size (blocks) for the current device
+// Batched persistent kernel over a work list. `packed` holds the slot-layout
+// sources (n_slots x (comp ? 2 : 1) float4), written here when b.need_pack;
+// `counters` holds kBatchedModes ints reset by a fill kernel first.
+hipError_t launch_pair_batched(const BatchedArgs &b, const double *pos, const double *mass,
+                               float4 *packed, double G, int *counters, double *acc, double *pot,
+                               hipStream_t stream);
+int batched_grid(bool comp, int mode);  // persistent grid (blocks) for the current device
 
 // FP64 integrator and diagnostics.
 hipError_t launch_kick_drift(double *pos, double *vel, const double *acc, int64_t n, double h,

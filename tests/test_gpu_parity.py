@@ -321,6 +321,32 @@ def test_batched_matches_per_cluster_oracle(variant):
     plan.close()
 
 
+@pytest.mark.parametrize("variant", ["comp", "plain"])
+def test_batched_every_mode(variant, tmp_path):
+    """Every compiled batched mode (LDS-tiled and scalar-stream shapes),
+    forced for all cluster sizes, matches the per-cluster oracle and is
+    bitwise reproducible."""
+    ens = _small_ensemble(k=10, seed=17)
+    ref_a, ref_p = _batched_ref(ens)
+    v = nbody.VARIANTS[variant]
+    try:
+        for mode in range(len(nbody.batched_modes())):
+            path = tmp_path / f"mode{mode}.txt"
+            path.write_text("".join(f"batched {v} {c} {mode}\n" for c in range(48)))
+            plan = nbody.Plan(ens.offsets, ens.eps, variant, tune_path=str(path))
+            a1, p1 = plan.accel(T(ens.pos), T(ens.mass))
+            a2, p2 = plan.accel(T(ens.pos), T(ens.mass))
+            torch.cuda.synchronize()
+            a1, p1, a2, p2 = (x.cpu().numpy() for x in (a1, p1, a2, p2))
+            assert np.array_equal(a1, a2) and np.array_equal(p1, p2), mode
+            for c in range(len(ens.sizes)):
+                s, e = ens.offsets[c], ens.offsets[c + 1]
+                check(a1[s:e], p1[s:e], ref_a[s:e], ref_p[s:e], what=(variant, mode, c))
+            plan.close()
+    finally:
+        nbody.tune_reset()
+
+
 def test_batched_leakage():
     """All clusters sit at the origin: if any pair crossed a cluster boundary
     the error would be of order one, not 1e-6."""
