@@ -56,7 +56,80 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--full-run", action="store_true",
+                    help="run the workload's whole step count and report time-to-solution, "
+                         "energy/momentum drift and the final-state force error")
     return ap.parse_args()
+
+
+def full_run(name, variant, steps=None):
+    """The workload's complete run: initial force, all KDK steps with a
+    diagnostics row each, then the final-state accelerations against the FP64
+    oracle on 4096 strided targets (per cluster for the ensemble)."""
+    import torch
+
+    from oracle import cpu as ocpu
+    from oracle import oracle as orc
+    from paper_2509_19294_amd import ics, nbody
+
+    nbody.load()
+    dev = torch.device("cuda:0")
+    plan = None
+    if name == "ensemble_512":
+        ens, spec = ics.workload(name)
+        pos, vel, mass, eps = ens.pos, ens.vel, ens.mass, 0.0
+        plan = nbody.Plan(ens.offsets, ens.eps, variant)
+        pairs = plan.pairs
+    else:
+        pos, vel, mass, spec = ics.workload(name)
+        eps = spec["eps"]
+        pairs = float(len(mass)) ** 2
+    steps = spec["steps"] if steps is None else steps
+    tp, tv, tm = (torch.from_numpy(x).to(dev) for x in (pos, vel, mass))
+    pot = torch.empty_like(tm)
+    diag = torch.empty((steps, nbody.DIAG_LEN), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if plan is not None:
+        acc, _ = plan.accel(tp, tm, 1.0, pot=pot)
+    else:
+        acc, _ = nbody.accel(tp, tm, eps, 1.0, variant, pot=pot)
+    # initial energy from the same kernels
+    d0 = torch.empty((1, nbody.DIAG_LEN), dtype=torch.float64, device=dev)
+    nbody.step(tp, tv, acc, tm, eps, 1.0, 0.0, 1, variant, plan=plan, diag=d0, pot=pot)
+    nbody.step(tp, tv, acc, tm, eps, 1.0, spec["dt"], steps, variant, plan=plan, diag=diag, pot=pot)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    d = diag.cpu().numpy()
+    e0 = float(d0.cpu().numpy()[0, 2])
+    de = np.abs(d[:, 2] - e0) / abs(e0)
+    pf, af = tp.cpu().numpy(), acc.cpu().numpy()
+    if plan is not None:
+        k = int(np.argsort(ens.sizes)[len(ens.sizes) // 2])
+        s, e = int(ens.offsets[k]), int(ens.offsets[k + 1])
+        ref_a, _ = ocpu.accel_pot(pf[s:e], mass[s:e], float(ens.eps[k]))
+        a_s = af[s:e]
+        where = f"cluster {k} ({e - s} particles), all targets"
+    else:
+        tgt = orc.subsample_targets(len(mass), 4096)
+        ref_a, _ = ocpu.accel_pot(pf, mass, eps, targets=tgt)
+        a_s = af[tgt]
+        where = f"{len(tgt)} strided targets"
+    out = {
+        "full_run": name, "variant": variant, "steps": steps, "dt": spec["dt"],
+        "force_evaluations": steps + 2, "time_to_solution_s": round(wall, 3),
+        "G_pair_per_s": round(pairs * (steps + 2) / wall / 1e9, 1),
+        "energy_drift_final": float(f"{de[-1]:.3e}"), "energy_drift_max": float(f"{de.max():.3e}"),
+        "momentum_max": float(f"{np.abs(d[:, 3:6]).max():.3e}"),
+        "angular_momentum_change_max": float(f"{np.abs(d[:, 6:9] - d[0, 6:9]).max():.3e}"),
+        "nonfinite": int(d[:, 13].max()),
+        "final_acc_rel_rms": float(f"{orc.rel_rms(a_s, ref_a):.3e}"),
+        "final_acc_max_rel": float(f"{orc.max_rel(a_s, ref_a):.3e}"),
+        "final_check": where,
+    }
+    print(json.dumps(out), flush=True)
+    if plan is not None:
+        plan.close()
 
 
 def cpu_baseline(pos, mass, eps, budget_s):
@@ -126,6 +199,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.full_run:
+        full_run(args.workload, args.variant or DEFAULT_VARIANT[args.workload])
         return
 
     import torch

@@ -1,0 +1,44 @@
+// Device helpers shared by the pair kernels (kernels.hip, kernels_sym.hip).
+#pragma once
+
+#include "nbody_internal.h"
+
+namespace nb {
+
+// Hardware reciprocal square root (v_rsq_f32, about 1 ulp).
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Knuth's TwoSum: s + e == a + b exactly (round-to-nearest, no overflow).
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Double-single split of an FP64 offset: hi = fp32(d), lo = fp32(d - hi).
+__device__ __forceinline__ void ds_split(double d, float &hi, float &lo) {
+  hi = static_cast<float>(d);
+  lo = static_cast<float>(d - static_cast<double>(hi));
+}
+
+// Destination of a block's results.
+struct OutArgs {
+  double *acc;       // [n][3] or nullptr when writing partials
+  double *pot;       // [n] or nullptr
+  float4 *part;      // grid j-split partials, nullptr when writing acc/pot
+  int64_t n;         // stride of one split in `part`
+  int split_index;
+  double G;
+};
+
+// Self-pair term the kernel adds to the potential sum when eps > 0 (the pair
+// j == i contributes m_i * rsq(eps^2) and nothing to the acceleration); it is
+// removed again in FP64. The expression matches the in-loop one bit for bit.
+__device__ __forceinline__ float self_term(float m, float eps2f) { return m * rsq(eps2f); }
+
+// Four consecutive float4 words, 64-byte aligned: one scalar load.
+struct alignas(64) Quad {
+  float4 v[4];
+};
+
+}  // namespace nb

@@ -21,33 +21,13 @@
 // double-single coordinates relative to an FP64 frame (the first i of the
 // block): hi = fp32(x - c), lo = fp32((x - c) - hi); a separation is
 // (hi_j - hi_i) + (lo_j - lo_i).
-#include "nbody_internal.h"
+#include "device_common.h"
 
 namespace nb {
 
-__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// Knuth's TwoSum: s + e == a + b exactly (round-to-nearest, no overflow).
-__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
-  s = a + b;
-  const float bb = s - a;
-  e = (a - (s - bb)) + (b - bb);
-}
 
-// Destination of a block's results.
-struct OutArgs {
-  double *acc;       // [n][3] or nullptr when writing partials
-  double *pot;       // [n] or nullptr
-  float4 *part;      // grid j-split partials, nullptr when writing acc/pot
-  int64_t n;         // stride of one split in `part`
-  int split_index;
-  double G;
-};
 
-// Self-pair term the kernel adds to the potential sum when eps > 0 (the pair
-// j == i contributes m_i * rsq(eps^2) and nothing to the acceleration); it is
-// removed again in FP64. The expression matches the in-loop one bit for bit.
-__device__ __forceinline__ float self_term(float m, float eps2f) { return m * rsq(eps2f); }
 
 template <bool COMP>
 struct StageRegs;
@@ -82,10 +62,6 @@ __device__ __forceinline__ void stage_load(StageRegs<COMP> &r, const double *__r
   }
 }
 
-__device__ __forceinline__ void ds_split(double d, float &hi, float &lo) {
-  hi = static_cast<float>(d);
-  lo = static_cast<float>(d - static_cast<double>(hi));
-}
 
 template <bool COMP>
 __device__ __forceinline__ void stage_store(float4 *dst, const StageRegs<COMP> &r, double cx,
@@ -420,10 +396,6 @@ __global__ __launch_bounds__(256) void pack_ds_kernel(const double *__restrict__
   out[2 * i + 1] = make_float4(lx, ly, lz, 0.f);
 }
 
-// Four consecutive float4 words, 64-byte aligned: one scalar load.
-struct alignas(64) Quad {
-  float4 v[4];
-};
 
 // Scalar-stream form of the pair kernel. The source index is the same for
 // every lane of a wave, so each wave streams its sources straight from the
