@@ -14,12 +14,62 @@
 //     softened interaction (3 sub, 3 fma, rsq, 3 mul, 4 fma/add) against
 //     register-resident source values that change every iteration
 //  11 ds_read_b128 broadcast + 4 fma_f32
+//  12 symmetric pair arithmetic with lane rotation: each lane holds ILP
+//     targets and one source; 16 steps per iteration read the source through
+//     a DPP row rotation (free on VOP2 instructions) and add the source-side
+//     contribution back through the inverse rotation; one evaluation serves
+//     two interactions
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace {
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+template <int CTRL>
+__device__ __forceinline__ float dppf(float x) {
+  if constexpr (CTRL == 0) return x;
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xf, 0xf, true));
+}
+
+// One rotation step r: targets (per lane) against the source r lanes away
+// within the row; the source-side sums go back through the inverse rotation.
+template <int ILP, int R>
+__device__ __forceinline__ void rot_step(float (&tx)[ILP], float (&ty)[ILP], float (&tz)[ILP],
+                                         float (&tm)[ILP], float (&ax)[ILP], float (&ay)[ILP],
+                                         float (&az)[ILP], float (&ap)[ILP], float sx, float sy,
+                                         float sz, float sm, float &bx, float &by, float &bz,
+                                         float &bp, float e2) {
+  constexpr int FWD = R == 0 ? 0 : 0x120 + R;          // row_ror:R
+  constexpr int BWD = R == 0 ? 0 : 0x120 + (16 - R);   // row_ror:16-R
+  const float xs = dppf<FWD>(sx), ys = dppf<FWD>(sy), zs = dppf<FWD>(sz), ms = dppf<FWD>(sm);
+  float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
+#pragma unroll
+  for (int k = 0; k < ILP; ++k) {
+    const float dx = xs - tx[k], dy = ys - ty[k], dz = zs - tz[k];
+    float r2 = fmaf(dx, dx, e2);
+    r2 = fmaf(dy, dy, r2);
+    r2 = fmaf(dz, dz, r2);
+    const float rho = rsq(r2);
+    const float rho2 = rho * rho;
+    const float mr = ms * rho;
+    const float si = mr * rho2;
+    ax[k] = fmaf(si, dx, ax[k]);
+    ay[k] = fmaf(si, dy, ay[k]);
+    az[k] = fmaf(si, dz, az[k]);
+    ap[k] += mr;
+    const float mj = tm[k] * rho;
+    const float sj = mj * rho2;
+    c0 = fmaf(-sj, dx, c0);
+    c1 = fmaf(-sj, dy, c1);
+    c2 = fmaf(-sj, dz, c2);
+    c3 += mj;
+  }
+  bx += dppf<BWD>(c0);
+  by += dppf<BWD>(c1);
+  bz += dppf<BWD>(c2);
+  bp += dppf<BWD>(c3);
+}
 
 template <int OP, int ILP>
 __global__ __launch_bounds__(1024) void mb_kernel(float *out, int iters, float seed) {
@@ -41,6 +91,7 @@ __global__ __launch_bounds__(1024) void mb_kernel(float *out, int iters, float s
     __syncthreads();
   }
   float sx = 0.1f + tf, sy = 0.2f, sz = -0.3f, sm = 1e-3f, e2 = 1e-4f;
+  float d2[4] = {0.f, 0.f, 0.f, 0.f};
   for (int it = 0; it < iters; ++it) {
 #pragma unroll
     for (int k = 0; k < ILP; ++k) {
@@ -80,6 +131,8 @@ __global__ __launch_bounds__(1024) void mb_kernel(float *out, int iters, float s
         ay[k] = fmaf(s, dy, ay[k]);
         az[k] = fmaf(s, dz, az[k]);
         ap[k] += mr;
+      } else if constexpr (OP == 12) {
+        // handled below, once per iteration
       } else if constexpr (OP == 11) {
         const float4 t = tile[(it * ILP + k) & 255];
         a[k] = fmaf(a[k], t.y, t.z);
@@ -93,11 +146,40 @@ __global__ __launch_bounds__(1024) void mb_kernel(float *out, int iters, float s
       sx = sx * 0.999f + 1e-3f;
       sy = sy * 0.999f - 1e-3f;
     }
+    if constexpr (OP == 12) {
+      float tz[ILP], tm[ILP];
+#pragma unroll
+      for (int k = 0; k < ILP; ++k) {
+        tz[k] = a[k] * 0.5f;
+        tm[k] = 1e-3f;
+      }
+      rot_step<ILP, 0>(a, y, tz, tm, ax, ay, az, ap, sx, sy, sz, sm, d2[0], d2[1], d2[2], d2[3], e2);
+      rot_step<ILP, 1>(a, y, tz, tm, ax, ay, az, ap, sx, sy, sz, sm, d2[0], d2[1], d2[2], d2[3], e2);
+      rot_step<ILP, 2>(a, y, tz, tm, ax, ay, az, ap, sx, sy, sz, sm, d2[0], d2[1], d2[2], d2[3], e2);
+      rot_step<ILP, 3>(a, y, tz, tm, ax, ay, az, ap, sx, sy, sz, sm, d2[0], d2[1], d2[2], d2[3], e2);
+      rot_step<ILP, 4>(a, y, tz, tm, ax, ay, az, ap, sx, sy, sz, sm, d2[0], d2[1], d2[2], d2[3], e2);
+      rot_step<ILP, 5>(a, y, tz, tm, ax, ay, az, ap, sx, sy, sz, sm, d2[0], d2[1], d2[2], d2[3], e2);
+      rot_step<ILP, 6>(a, y, tz, tm, ax, ay, az, ap, sx, sy, sz, sm, d2[0], d2[1], d2[2], d2[3], e2);
+      rot_step<ILP, 7>(a, y, tz, tm, ax, ay, az, ap, sx, sy, sz, sm, d2[0], d2[1], d2[2], d2[3], e2);
+      rot_step<ILP, 8>(a, y, tz, tm, ax, ay, az, ap, sx, sy, sz, sm, d2[0], d2[1], d2[2], d2[3], e2);
+      rot_step<ILP, 9>(a, y, tz, tm, ax, ay, az, ap, sx, sy, sz, sm, d2[0], d2[1], d2[2], d2[3], e2);
+      rot_step<ILP, 10>(a, y, tz, tm, ax, ay, az, ap, sx, sy, sz, sm, d2[0], d2[1], d2[2], d2[3], e2);
+      rot_step<ILP, 11>(a, y, tz, tm, ax, ay, az, ap, sx, sy, sz, sm, d2[0], d2[1], d2[2], d2[3], e2);
+      rot_step<ILP, 12>(a, y, tz, tm, ax, ay, az, ap, sx, sy, sz, sm, d2[0], d2[1], d2[2], d2[3], e2);
+      rot_step<ILP, 13>(a, y, tz, tm, ax, ay, az, ap, sx, sy, sz, sm, d2[0], d2[1], d2[2], d2[3], e2);
+      rot_step<ILP, 14>(a, y, tz, tm, ax, ay, az, ap, sx, sy, sz, sm, d2[0], d2[1], d2[2], d2[3], e2);
+      rot_step<ILP, 15>(a, y, tz, tm, ax, ay, az, ap, sx, sy, sz, sm, d2[0], d2[1], d2[2], d2[3], e2);
+      sx = sx * 0.999f + 1e-3f;
+      sy = sy * 0.999f - 1e-3f;
+      sz = sz * 0.999f + 2e-3f;
+      sm = sm * 0.9999f;
+    }
   }
   float s = 0.f;
 #pragma unroll
   for (int k = 0; k < ILP; ++k)
     s += a[k] + y[k] + static_cast<float>(d[k]) + ax[k] + ay[k] + az[k] + ap[k];
+  s += d2[0] + d2[1] + d2[2] + d2[3];
   out[static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x] = s;
 }
 
@@ -121,7 +203,8 @@ hipError_t launch_op(int op, float *out, int blocks, int threads, int iters) {
     case 8: return launch<8, ILP>(out, blocks, threads, iters);
     case 9: return launch<9, ILP>(out, blocks, threads, iters);
     case 10: return launch<10, ILP>(out, blocks, threads, iters);
-    default: return launch<11, ILP>(out, blocks, threads, iters);
+    case 11: return launch<11, ILP>(out, blocks, threads, iters);
+    default: return launch<12, ILP>(out, blocks, threads, iters);
   }
 }
 
@@ -136,7 +219,7 @@ extern "C" {
 // Returns 0 on success, -1 on bad arguments, else the HIP error code.
 int mb_run(int op, int ilp, float *out, int blocks, int threads, int iters, int reps,
            double *ms_out) {
-  if (op < 0 || op > 11 || reps < 1 || reps > 64 || !out || !ms_out || blocks < 1 ||
+  if (op < 0 || op > 12 || reps < 1 || reps > 64 || !out || !ms_out || blocks < 1 ||
       threads < 64 || threads > 1024 || threads % 64 != 0 || iters < 1)
     return -1;
   if (ilp != 1 && ilp != 2 && ilp != 4 && ilp != 8 && ilp != 16) return -1;

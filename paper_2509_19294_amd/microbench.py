@@ -36,6 +36,7 @@ OPS = {
     9: ("13fma_f32+rsq_f32", 14),
     10: ("pair_arith", 14),
     11: ("lds_bcast+4fma_f32", 5),
+    12: ("sym_rot_pair_arith", 16 * 19),   # per chain-iteration: 16 pair evaluations
 }
 
 # (op, ilp, blocks, threads)
@@ -49,6 +50,7 @@ CASES = [
     (10, 1, 4096, 256), (10, 2, 4096, 256), (10, 4, 4096, 256), (10, 8, 4096, 256),
     (10, 2, 512, 256), (10, 4, 512, 256), (10, 4, 256, 256), (10, 8, 256, 256),
     (11, 8, 4096, 256),
+    (12, 2, 4096, 256), (12, 4, 4096, 256), (12, 8, 4096, 256), (12, 4, 1024, 256),
 ]
 
 
@@ -88,8 +90,11 @@ def run(reps: int = 5, clock_ghz: float = 2.4, target: float = 3e10):
         row = {"op": name, "ilp": ilp, "blocks": blocks, "threads": threads,
                "waves_per_simd": round(waves_per_simd, 2), "ms": round(ms.value, 4),
                "lane_instr_per_cu_clk": round(rate / (cus * clock_ghz * 1e9), 2)}
-        if op == 10:
-            inter = float(blocks) * threads * iters * ilp / (ms.value * 1e-3)
+        if op in (10, 12):
+            # each symmetric evaluation serves two interactions
+            per_eval = 2 if op == 12 else 1
+            evals = 16 if op == 12 else 1
+            inter = float(blocks) * threads * iters * ilp * evals * per_eval / (ms.value * 1e-3)
             row["G_interactions_per_s"] = round(inter / 1e9, 1)
             row["pct_fp32_peak_at_20_flops"] = round(100 * 20 * inter / 157.3e12, 1)
         rows.append(row)
