@@ -43,6 +43,9 @@ def _load():
         lib.oracle_kdk.argtypes = [dp, dp, dp, dp, dp, ctypes.c_int64, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int]
         lib.oracle_kdk.restype = None
+        lib.oracle_accel_jerk.argtypes = [dp, dp, dp, ctypes.c_int64, ip, ctypes.c_int64,
+                                          ctypes.c_double, ctypes.c_double, dp, dp, dp, ctypes.c_int]
+        lib.oracle_accel_jerk.restype = None
         lib.oracle_max_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -95,3 +98,28 @@ def kdk(pos, vel, mass, eps, G, dt, n_steps, acc=None, nthreads=0):
     lib.oracle_kdk(_dptr(pos), _dptr(vel), _dptr(acc), _dptr(pot), _dptr(mass), n,
                    float(eps), float(G), float(dt), int(n_steps), int(nthreads))
     return pos, vel, acc, pot
+
+
+def accel_jerk(pos, vel, mass, eps=0.0, G=1.0, targets=None, nthreads=0):
+    """Same contract as ``oracle.oracle.accel_jerk``, summed sequentially in C."""
+    lib = _load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    vel = np.ascontiguousarray(vel, dtype=np.float64)
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    n = pos.shape[0]
+    if targets is None:
+        tgt, nt = None, n
+    else:
+        tgt = np.ascontiguousarray(targets, dtype=np.int64)
+        nt = tgt.shape[0]
+        if nt and (tgt.min() < 0 or tgt.max() >= n):
+            raise IndexError("target index out of range")
+    acc = np.zeros((nt, 3))
+    jerk = np.zeros((nt, 3))
+    pot = np.zeros(nt)
+    if nt == 0:
+        return acc, jerk, pot
+    lib.oracle_accel_jerk(_dptr(pos), _dptr(vel), _dptr(mass), n,
+                          None if tgt is None else tgt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                          nt, float(eps), float(G), _dptr(acc), _dptr(jerk), _dptr(pot), int(nthreads))
+    return acc, jerk, pot

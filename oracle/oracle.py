@@ -19,6 +19,16 @@ What it computes, and where that comes from:
   v += dt/2 a; x += dt v; a = A(x); v += dt/2 a.
 * Diagnostics: K = 1/2 sum m |v|^2, W = 1/2 sum m phi, E = K + W, total
   momentum P = sum m v, angular momentum L = sum m x cross v, centre of mass.
+* Jerk (Section 3 names it beside the acceleration as the other quantity
+  the device computes; the paper does not print its formula). It is the time
+  derivative of the softened acceleration: with d = x_j - x_i,
+  w = v_j - v_i and q = r^2 + eps^2,
+  jerk_i = G sum_{j != i} m_j [w / q^{3/2} - 3 (d.w) d / q^{5/2}].
+* Fourth-order Hermite predictor-corrector with a shared step (the scheme
+  jerk is used for; the paper does not name its integrator): predict
+  x_p = x + v dt + a dt^2/2 + j dt^3/6, v_p = v + a dt + j dt^2/2; evaluate
+  a_1, j_1 at (x_p, v_p); correct v_1 = v + (a_0 + a_1) dt/2 + (j_0 - j_1) dt^2/12,
+  x_1 = x + (v + v_1) dt/2 + (a_0 - a_1) dt^2/12.
 * Error metrics used to judge the GPU results against this oracle.
 
 Everything is float64. Sums over j use numpy reductions of whole rows (a
@@ -91,6 +101,89 @@ def accel_pot(pos, mass, eps=0.0, G=1.0, targets=None, chunk=None):
         acc[s:s + chunk] = G * np.einsum("cj,cjk->ck", w3, d)
         pot[s:s + chunk] = -G * w.sum(axis=1)
     return acc, pot
+
+
+def brute_force_jerk(pos, vel, mass, eps=0.0, G=1.0):
+    """Pure-Python double loop for the jerk, for tiny N only."""
+    n = len(mass)
+    jerk = [[0.0, 0.0, 0.0] for _ in range(n)]
+    for i in range(n):
+        for j in range(n):
+            if j == i:
+                continue
+            d = [pos[j][c] - pos[i][c] for c in range(3)]
+            w = [vel[j][c] - vel[i][c] for c in range(3)]
+            q = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps * eps
+            dw = d[0] * w[0] + d[1] * w[1] + d[2] * w[2]
+            for c in range(3):
+                jerk[i][c] += G * mass[j] * (w[c] / q ** 1.5 - 3.0 * dw * d[c] / q ** 2.5)
+    return np.array(jerk, dtype=np.float64)
+
+
+def accel_jerk(pos, vel, mass, eps=0.0, G=1.0, targets=None, chunk=None):
+    """Accelerations, jerks and potentials on ``targets`` (all if None),
+    self term excluded by index. Returns ``(acc, jerk, pot)``."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    vel = np.ascontiguousarray(vel, dtype=np.float64)
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    n = pos.shape[0]
+    t_idx = np.arange(n) if targets is None else np.asarray(targets, dtype=np.int64)
+    nt = t_idx.shape[0]
+    acc = np.zeros((nt, 3))
+    jerk = np.zeros((nt, 3))
+    pot = np.zeros(nt)
+    if n == 0 or nt == 0:
+        return acc, jerk, pot
+    if chunk is None:
+        chunk = max(1, min(nt, (1 << 22) // max(n, 1)))
+    eps2 = float(eps) * float(eps)
+    for s in range(0, nt, chunk):
+        ti = t_idx[s:s + chunk]
+        d = pos[None, :, :] - pos[ti, None, :]
+        w = vel[None, :, :] - vel[ti, None, :]
+        q = np.einsum("cjk,cjk->cj", d, d) + eps2
+        self_mask = np.arange(n)[None, :] == ti[:, None]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            inv = 1.0 / np.sqrt(q)
+        inv = np.where(self_mask, 0.0, inv)
+        m1 = mass[None, :] * inv                 # m / q^{1/2}
+        m3 = m1 * inv * inv                      # m / q^{3/2}
+        m5 = m3 * inv * inv                      # m / q^{5/2}
+        dw = np.einsum("cjk,cjk->cj", d, w)
+        acc[s:s + chunk] = G * np.einsum("cj,cjk->ck", m3, d)
+        jerk[s:s + chunk] = G * (np.einsum("cj,cjk->ck", m3, w) - 3.0 * np.einsum("cj,cjk->ck", m5 * dw, d))
+        pot[s:s + chunk] = -G * m1.sum(axis=1)
+    return acc, jerk, pot
+
+
+def hermite(pos, vel, mass, eps, G, dt, n_steps, acc=None, jerk=None, force=None, diag=True):
+    """Fourth-order Hermite predictor-corrector, shared step, FP64.
+
+    ``force(x, v) -> (acc, jerk, pot)`` defaults to the softened direct sum.
+    Returns ``(pos, vel, acc, jerk, pot, rows)``; the potential of a row is the
+    one evaluated at that step's predicted positions."""
+    if force is None:
+        def force(x, v):
+            return accel_jerk(x, v, mass, eps, G)
+    pos = np.array(pos, dtype=np.float64)
+    vel = np.array(vel, dtype=np.float64)
+    if acc is None or jerk is None:
+        acc, jerk, pot = force(pos, vel)
+    else:
+        acc = np.array(acc, dtype=np.float64)
+        jerk = np.array(jerk, dtype=np.float64)
+        pot = force(pos, vel)[2] if diag else None
+    rows = [diagnostics(pos, vel, mass, pot, step=0)] if diag else None
+    for s in range(n_steps):
+        xp = pos + dt * vel + (dt * dt / 2.0) * acc + (dt ** 3 / 6.0) * jerk
+        vp = vel + dt * acc + (dt * dt / 2.0) * jerk
+        a1, j1, pot = force(xp, vp)
+        v1 = vel + (dt / 2.0) * (acc + a1) + (dt * dt / 12.0) * (jerk - j1)
+        x1 = pos + (dt / 2.0) * (vel + v1) + (dt * dt / 12.0) * (acc - a1)
+        pos, vel, acc, jerk = x1, v1, a1, j1
+        if diag:
+            rows.append(diagnostics(pos, vel, mass, pot, step=s + 1))
+    return pos, vel, acc, jerk, pot, (np.array(rows) if diag else None)
 
 
 def kdk(pos, vel, mass, eps, G, dt, n_steps, acc=None, accel=None, diag=True):

@@ -71,4 +71,49 @@ void oracle_kdk(double *pos, double *vel, double *acc, double *pot,
     }
 }
 
+/* Accelerations, jerks (time derivative of the acceleration) and
+ * potentials: jerk_i = G sum_{j != i} m_j [w/q^{3/2} - 3 (d.w) d/q^{5/2}],
+ * d = x_j - x_i, w = v_j - v_i, q = |d|^2 + eps^2. */
+void oracle_accel_jerk(const double *pos, const double *vel, const double *mass, int64_t n,
+                       const int64_t *targets, int64_t nt, double eps, double G,
+                       double *acc, double *jerk, double *pot, int nthreads)
+{
+    const double eps2 = eps * eps;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t i = targets ? targets[t] : t;
+        double ax = 0.0, ay = 0.0, az = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, ph = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double dx = pos[3 * j] - pos[3 * i];
+            const double dy = pos[3 * j + 1] - pos[3 * i + 1];
+            const double dz = pos[3 * j + 2] - pos[3 * i + 2];
+            const double wx = vel[3 * j] - vel[3 * i];
+            const double wy = vel[3 * j + 1] - vel[3 * i + 1];
+            const double wz = vel[3 * j + 2] - vel[3 * i + 2];
+            const double q = dx * dx + dy * dy + dz * dz + eps2;
+            const double r = sqrt(q);
+            const double m1 = mass[j] / r;
+            const double m3 = m1 / q;
+            const double m5 = m3 / q;
+            const double dw = dx * wx + dy * wy + dz * wz;
+            ax += m3 * dx;
+            ay += m3 * dy;
+            az += m3 * dz;
+            jx += m3 * wx - 3.0 * m5 * dw * dx;
+            jy += m3 * wy - 3.0 * m5 * dw * dy;
+            jz += m3 * wz - 3.0 * m5 * dw * dz;
+            ph -= m1;
+        }
+        acc[3 * t] = G * ax;
+        acc[3 * t + 1] = G * ay;
+        acc[3 * t + 2] = G * az;
+        jerk[3 * t] = G * jx;
+        jerk[3 * t + 1] = G * jy;
+        jerk[3 * t + 2] = G * jz;
+        if (pot) pot[t] = G * ph;
+    }
+}
+
 int oracle_max_threads(void) { return omp_get_max_threads(); }

@@ -55,3 +55,35 @@ def test_unmutated_oracle_passes():
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_planted_mistake_is_caught(name):
     assert not _pins_pass(_mutant(*MUTATIONS[name]))
+
+
+JERK_MUTATIONS = {
+    "relative_velocity_sign": ("w = vel[None, :, :] - vel[ti, None, :]", "w = vel[ti, None, :] - vel[None, :, :]"),
+    "factor_three_dropped": ("- 3.0 * np.einsum(\"cj,cjk->ck\", m5 * dw, d)", "- np.einsum(\"cj,cjk->ck\", m5 * dw, d)"),
+    "second_term_sign": ("jerk[s:s + chunk] = G * (np.einsum(\"cj,cjk->ck\", m3, w) - 3.0",
+                         "jerk[s:s + chunk] = G * (np.einsum(\"cj,cjk->ck\", m3, w) + 3.0"),
+    "wrong_power": ("m5 = m3 * inv * inv", "m5 = m3 * inv"),
+}
+
+
+def _jerk_mutant(old, new):
+    src = textwrap.dedent(inspect.getsource(orc.accel_jerk))
+    assert old in src, old
+    ns = {"np": np}
+    exec(compile(src.replace(old, new), "<mutant>", "exec"), ns)
+    return ns["accel_jerk"]
+
+
+def _jerk_pin_passes(f):
+    g = golden_io.load("three_body_eps0.txt")
+    _, jerk, _ = f(golden_io.arr(g, "pos"), golden_io.arr(g, "vel"), golden_io.arr(g, "mass")[0], 0.0, 1.0)
+    return np.allclose(jerk, golden_io.arr(g, "jerk"), rtol=0, atol=1e-15)
+
+
+def test_unmutated_jerk_passes():
+    assert _jerk_pin_passes(orc.accel_jerk)
+
+
+@pytest.mark.parametrize("name", sorted(JERK_MUTATIONS))
+def test_planted_jerk_mistake_is_caught(name):
+    assert not _jerk_pin_passes(_jerk_mutant(*JERK_MUTATIONS[name]))
