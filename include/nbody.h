@@ -176,6 +176,42 @@ nbody_status nbody_tune_load(const char *path);
  * every forced configuration. */
 nbody_status nbody_tune_reset(void);
 
+/* ---- acceleration + jerk and the Hermite integrator ----------------------
+ * The paper's device computes the jerk (the time derivative of the
+ * acceleration) beside the force (Section 3). With d = x_j - x_i,
+ * w = v_j - v_i and q = |d|^2 + eps^2:
+ *     jerk_i = G sum_{j != i} m_j [w q^{-3/2} - 3 (d.w) d q^{-5/2}].
+ * Pair arithmetic is FP32 (the compensated form uses double-single
+ * positions relative to particle 0 and velocities relative to particle 0's);
+ * outputs are FP64. */
+
+/* Workspace bytes for nbody_accel_jerk / nbody_step_hermite (0 for invalid
+ * arguments). */
+size_t nbody_workspace_bytes_jerk(int64_t n, int32_t variant);
+
+/* Accelerations, jerks and potentials of one system.
+ *   pos, vel [n][3] f64 in; mass [n] f64 in; acc, jerk [n][3] f64 out;
+ *   pot [n] f64 out or NULL. Other arguments and errors as nbody_accel;
+ *   ws_bytes >= nbody_workspace_bytes_jerk(n, variant). */
+nbody_status nbody_accel_jerk(const double *pos, const double *vel, const double *mass, int64_t n,
+                              double eps, double G, int32_t variant, double *acc, double *jerk,
+                              double *pot, void *ws, size_t ws_bytes, void *stream);
+
+/* n_steps of the fourth-order Hermite predictor-corrector with a shared
+ * step, FP64 on the GPU (Makino and Aarseth 1992): predict
+ * x_p = x + v dt + a dt^2/2 + j dt^3/6, v_p = v + a dt + j dt^2/2; evaluate
+ * a_1, j_1 at (x_p, v_p); correct v_1 = v + (a + a_1) dt/2 + (j - j_1) dt^2/12,
+ * x_1 = x + (v + v_1) dt/2 + (a - a_1) dt^2/12.
+ *   acc, jerk must hold A(pos, vel) and J(pos, vel) on entry (call
+ *   nbody_accel_jerk first) and hold a_1, j_1 of the last step on return.
+ *   pot (nullable) and the diagnostics' W use the potentials evaluated at the
+ *   predicted positions of the step. diag as for nbody_step.
+ *   ws_bytes >= nbody_workspace_bytes_jerk(n, variant). */
+nbody_status nbody_step_hermite(double *pos, double *vel, double *acc, double *jerk, double *pot,
+                                const double *mass, int64_t n, double eps, double G, double dt,
+                                int32_t n_steps, int32_t variant, double *diag, void *ws,
+                                size_t ws_bytes, void *stream);
+
 /* Kernel timing, for measurement. While enabled (on != 0), every
  * force-kernel launch made outside graph capture by nbody_accel, nbody_step
  * and nbody_accel_batched is bracketed by HIP events recorded on the stream

@@ -271,6 +271,53 @@ hipError_t enqueue_accel(const double *pos, const double *mass, int64_t n, doubl
                                 at<float4>(ws, L.part), st, stop);
 }
 
+// Workspace of the jerk / Hermite calls.
+struct JerkLayout {
+  size_t packed, part, xp, vp, a1, j1, pot, diag, ctr, total;
+};
+
+JerkLayout jerk_layout(int64_t n, int32_t variant) {
+  JerkLayout L{};
+  const size_t un = static_cast<size_t>(n);
+  const bool comp = variant == NBODY_FP32_COMP;
+  size_t off = 0;
+  L.packed = off;
+  off += align_up(static_cast<size_t>(nb::padded(n)) * (comp ? 3 : 2) * sizeof(float4));
+  L.part = off;
+  const int split = nb::jerk_split(n);
+  off += align_up(split > 1 ? static_cast<size_t>(split) * un * (comp ? 4 : 2) * sizeof(float4) : 0);
+  L.xp = off;
+  off += align_up(un * 3 * sizeof(double));
+  L.vp = off;
+  off += align_up(un * 3 * sizeof(double));
+  L.a1 = off;
+  off += align_up(un * 3 * sizeof(double));
+  L.j1 = off;
+  off += align_up(un * 3 * sizeof(double));
+  L.pot = off;
+  off += align_up(un * sizeof(double));
+  L.diag = off;
+  off += align_up(static_cast<size_t>(nb::kDiagBlocks) * nb::kDiagLen * sizeof(double));
+  L.ctr = off;
+  off += 256;
+  L.total = off;
+  return L;
+}
+
+hipError_t enqueue_accel_jerk(const double *pos, const double *vel, const double *mass, int64_t n,
+                              double eps, double G, int32_t variant, double *acc, double *jerk,
+                              double *pot, void *ws, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const JerkLayout L = jerk_layout(n, variant);
+  const bool comp = variant == NBODY_FP32_COMP;
+  float4 *packed = at<float4>(ws, L.packed);
+  hipError_t e = nb::launch_pack_jerk(pos, vel, mass, n, comp, packed, st);
+  if (e != hipSuccess) return e;
+  hipEvent_t stop = timing_begin(st);
+  return nb::launch_pair_jerk(comp, packed, mass, n, eps, G, nb::jerk_split(n), acc, jerk, pot,
+                              at<float4>(ws, L.part), st, stop);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -632,6 +679,91 @@ nbody_status nbody_step(double *pos, double *vel, double *acc, double *pot, cons
   }
   for (int32_t k = 0; k < n_steps && e == hipSuccess; ++k) e = hipGraphLaunch(plan->exec, s);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return NBODY_OK;
+}
+
+size_t nbody_workspace_bytes_jerk(int64_t n, int32_t variant) {
+  if (n < 0 || !valid_variant(variant)) return 0;
+  return jerk_layout(n, variant).total;
+}
+
+nbody_status nbody_accel_jerk(const double *pos, const double *vel, const double *mass, int64_t n,
+                              double eps, double G, int32_t variant, double *acc, double *jerk,
+                              double *pot, void *ws, size_t ws_bytes, void *stream) {
+  g_err.clear();
+  if (n < 0) return fail(NBODY_EINVAL, "n must be >= 0");
+  if (!valid_variant(variant)) return fail(NBODY_ENOTSUP, "unknown variant %d", variant);
+  nbody_status st = check_scalars(eps, G);
+  if (st != NBODY_OK) return st;
+  if (n == 0) return NBODY_OK;
+  if (!pos || !vel || !mass || !acc || !jerk)
+    return fail(NBODY_EINVAL, "pos, vel, mass, acc and jerk must be non-NULL");
+  const size_t b3 = static_cast<size_t>(n) * 3 * sizeof(double), b1 = static_cast<size_t>(n) * sizeof(double);
+  const void *ins[3] = {pos, vel, mass};
+  const size_t inb[3] = {b3, b3, b1};
+  void *outs[3] = {acc, jerk, pot};
+  const size_t outb[3] = {b3, b3, b1};
+  for (int a = 0; a < 3; ++a) {
+    for (int b = 0; b < 3; ++b)
+      if (overlap(outs[a], outb[a], ins[b], inb[b])) return fail(NBODY_EINVAL, "outputs overlap inputs");
+    for (int b = a + 1; b < 3; ++b)
+      if (overlap(outs[a], outb[a], outs[b], outb[b])) return fail(NBODY_EINVAL, "outputs overlap each other");
+  }
+  const size_t need = jerk_layout(n, variant).total;
+  if (!ws) return fail(NBODY_EWORKSPACE, "workspace is NULL (need %zu bytes)", need);
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(NBODY_EWORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < need) return fail(NBODY_EWORKSPACE, "workspace of %zu bytes < %zu required", ws_bytes, need);
+  const hipError_t e = enqueue_accel_jerk(pos, vel, mass, n, eps, G, variant, acc, jerk, pot, ws,
+                                          static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "nbody_accel_jerk launch");
+  return NBODY_OK;
+}
+
+nbody_status nbody_step_hermite(double *pos, double *vel, double *acc, double *jerk, double *pot,
+                                const double *mass, int64_t n, double eps, double G, double dt,
+                                int32_t n_steps, int32_t variant, double *diag, void *ws,
+                                size_t ws_bytes, void *stream) {
+  g_err.clear();
+  if (n < 0) return fail(NBODY_EINVAL, "n must be >= 0");
+  if (n_steps < 0) return fail(NBODY_EINVAL, "n_steps must be >= 0 (got %d)", n_steps);
+  if (!valid_variant(variant)) return fail(NBODY_ENOTSUP, "unknown variant %d", variant);
+  if (!std::isfinite(dt)) return fail(NBODY_EINVAL, "dt must be finite");
+  nbody_status st = check_scalars(eps, G);
+  if (st != NBODY_OK) return st;
+  if (n == 0 || n_steps == 0) return NBODY_OK;
+  if (!pos || !vel || !acc || !jerk || !mass)
+    return fail(NBODY_EINVAL, "pos, vel, acc, jerk and mass must be non-NULL");
+  const size_t b3 = static_cast<size_t>(n) * 3 * sizeof(double), b1 = static_cast<size_t>(n) * sizeof(double);
+  const void *arr[6] = {pos, vel, acc, jerk, mass, pot};
+  const size_t ab[6] = {b3, b3, b3, b3, b1, b1};
+  for (int a = 0; a < 6; ++a)
+    for (int b = a + 1; b < 6; ++b)
+      if (overlap(arr[a], ab[a], arr[b], ab[b])) return fail(NBODY_EINVAL, "arrays overlap");
+  if (diag) {
+    const size_t db = static_cast<size_t>(n_steps) * nb::kDiagLen * sizeof(double);
+    for (int a = 0; a < 6; ++a)
+      if (overlap(diag, db, arr[a], ab[a])) return fail(NBODY_EINVAL, "diag overlaps the state arrays");
+  }
+  const JerkLayout L = jerk_layout(n, variant);
+  if (!ws) return fail(NBODY_EWORKSPACE, "workspace is NULL (need %zu bytes)", L.total);
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(NBODY_EWORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total) return fail(NBODY_EWORKSPACE, "workspace of %zu bytes < %zu required", ws_bytes, L.total);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *xp = at<double>(ws, L.xp), *vp = at<double>(ws, L.vp);
+  double *a1 = at<double>(ws, L.a1), *j1 = at<double>(ws, L.j1);
+  double *potw = pot ? pot : (diag ? at<double>(ws, L.pot) : nullptr);
+  hipError_t e = hipSuccess;
+  if (diag) e = nb::launch_fill_int(at<int>(ws, L.ctr), 1, 0, s);
+  for (int32_t k = 0; k < n_steps && e == hipSuccess; ++k) {
+    e = nb::launch_hermite_predict(pos, vel, acc, jerk, n, dt, xp, vp, s);
+    if (e == hipSuccess) e = enqueue_accel_jerk(xp, vp, mass, n, eps, G, variant, a1, j1, potw, ws, s);
+    if (e == hipSuccess) e = nb::launch_hermite_correct(pos, vel, acc, jerk, a1, j1, n, dt, s);
+    if (e == hipSuccess && diag) {
+      e = nb::launch_kick_diag(pos, vel, nullptr, potw, mass, n, 0.0, at<double>(ws, L.diag), s);
+      if (e == hipSuccess) e = nb::launch_diag_final(at<double>(ws, L.diag), diag, at<int>(ws, L.ctr), s);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(e, "nbody_step_hermite launch");
   return NBODY_OK;
 }
 

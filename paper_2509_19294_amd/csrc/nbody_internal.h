@@ -100,6 +100,23 @@ hipError_t launch_pair_batched(const BatchedArgs &b, const double *pos, const do
                                hipStream_t stream);
 int batched_grid(bool comp, int mode);  // persistent grid (blocks) for the current device
 
+// Acceleration + jerk (kernels_jerk.hip). Packed sources hold 2 (plain) or
+// 3 (compensated) float4 per particle, padded(n) particles; partials hold
+// split x n x (2 or 4) float4.
+int jerk_split(int64_t n);
+hipError_t launch_pack_jerk(const double *pos, const double *vel, const double *mass, int64_t n,
+                            bool comp, float4 *packed, hipStream_t stream);
+hipError_t launch_pair_jerk(bool comp, const float4 *packed, const double *mass, int64_t n,
+                            double eps, double G, int split, double *acc, double *jerk,
+                            double *pot, float4 *part, hipStream_t stream,
+                            hipEvent_t after_pair = nullptr);
+hipError_t launch_hermite_predict(const double *pos, const double *vel, const double *acc,
+                                  const double *jerk, int64_t n, double dt, double *xp,
+                                  double *vp, hipStream_t stream);
+hipError_t launch_hermite_correct(double *pos, double *vel, double *acc, double *jerk,
+                                  const double *a1, const double *j1, int64_t n, double dt,
+                                  hipStream_t stream);
+
 // FP64 integrator and diagnostics.
 hipError_t launch_kick_drift(double *pos, double *vel, const double *acc, int64_t n, double h,
                              double dt, hipStream_t stream);

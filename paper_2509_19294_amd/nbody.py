@@ -71,6 +71,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
             "nbody_tune_get": (i32, [i32, i64]),
             "nbody_tune_load": (i32, [ctypes.c_char_p]),
             "nbody_tune_reset": (i32, []),
+            "nbody_workspace_bytes_jerk": (sz, [i64, i32]),
+            "nbody_accel_jerk": (i32, [c_dp, c_dp, c_dp, i64, dbl, dbl, i32, c_dp, c_dp, c_dp, c_dp,
+                                       sz, c_dp]),
+            "nbody_step_hermite": (i32, [c_dp, c_dp, c_dp, c_dp, c_dp, c_dp, i64, dbl, dbl, dbl, i32,
+                                         i32, c_dp, c_dp, sz, c_dp]),
             "nbody_timing_enable": (i32, [i32]),
             "nbody_timing_read": (i32, [ctypes.POINTER(i64), ctypes.POINTER(dbl)]),
         }
@@ -129,9 +134,10 @@ def workspace_bytes(n_total: int, n_clusters: int = 1, variant="plain") -> int:
 _ws_cache: dict = {}
 
 
-def workspace(n_total: int, n_clusters: int, variant, device) -> torch.Tensor:
+def workspace(n_total: int, n_clusters: int, variant, device, need: int | None = None) -> torch.Tensor:
     """A cached device workspace large enough for the call (allocated by torch)."""
-    need = workspace_bytes(n_total, n_clusters, variant)
+    if need is None:
+        need = workspace_bytes(n_total, n_clusters, variant)
     dev = torch.device(device)
     key = (dev.type, dev.index)
     ws = _ws_cache.get(key)
@@ -206,6 +212,64 @@ def step(pos, vel, acc, mass, eps: float, G: float, dt: float, n_steps: int, var
                         plan.handle if plan is not None else None,
                         diag.data_ptr() if (diag is not None and n_steps > 0) else None,
                         ws.data_ptr(), ws.numel(), _stream_handle(pos.device))
+    _check(st)
+    return diag
+
+
+def accel_jerk(pos, vel, mass, eps: float, G: float = 1.0, variant="plain", acc=None, jerk=None,
+               pot=True, ws=None):
+    """Accelerations, jerks and potentials of one system: nbody_accel_jerk.
+    Returns ``(acc, jerk, pot)``."""
+    lib = load()
+    _vec3(pos, "pos")
+    n = pos.shape[0]
+    _vec3(vel, "vel", n)
+    _vec1(mass, "mass", n)
+    acc = torch.empty_like(pos) if acc is None else _vec3(acc, "acc", n)
+    jerk = torch.empty_like(pos) if jerk is None else _vec3(jerk, "jerk", n)
+    if pot is True:
+        pot = torch.empty_like(mass)
+    elif pot is False:
+        pot = None
+    if pot is not None:
+        _vec1(pot, "pot", n)
+    v = _variant(variant)
+    if ws is None:
+        ws = workspace(n, 1, v, pos.device, need=int(lib.nbody_workspace_bytes_jerk(n, v)))
+    st = lib.nbody_accel_jerk(pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), n, float(eps), float(G), v,
+                              acc.data_ptr(), jerk.data_ptr(), pot.data_ptr() if pot is not None else None,
+                              ws.data_ptr(), ws.numel(), _stream_handle(pos.device))
+    _check(st)
+    return acc, jerk, pot
+
+
+def step_hermite(pos, vel, acc, jerk, mass, eps: float, G: float, dt: float, n_steps: int,
+                 variant="plain", diag: bool | torch.Tensor = True, pot=None, ws=None):
+    """``n_steps`` fourth-order Hermite steps in place: nbody_step_hermite.
+    ``acc`` and ``jerk`` must hold A and J at (pos, vel) on entry."""
+    lib = load()
+    _vec3(pos, "pos")
+    n = pos.shape[0]
+    for t, name in ((vel, "vel"), (acc, "acc"), (jerk, "jerk")):
+        _vec3(t, name, n)
+    _vec1(mass, "mass", n)
+    if pot is not None:
+        _vec1(pot, "pot", n)
+    v = _variant(variant)
+    if diag is True:
+        diag = torch.empty((max(int(n_steps), 0), DIAG_LEN), dtype=torch.float64, device=pos.device)
+    elif diag is False:
+        diag = None
+    if diag is not None and (diag.dtype != torch.float64 or diag.shape != (n_steps, DIAG_LEN)
+                             or not diag.is_contiguous()):
+        raise ValueError("diag must be a contiguous float64 tensor of shape (n_steps, 16)")
+    if ws is None:
+        ws = workspace(n, 1, v, pos.device, need=int(lib.nbody_workspace_bytes_jerk(n, v)))
+    st = lib.nbody_step_hermite(pos.data_ptr(), vel.data_ptr(), acc.data_ptr(), jerk.data_ptr(),
+                                pot.data_ptr() if pot is not None else None, mass.data_ptr(), n,
+                                float(eps), float(G), float(dt), int(n_steps), v,
+                                diag.data_ptr() if (diag is not None and n_steps > 0) else None,
+                                ws.data_ptr(), ws.numel(), _stream_handle(pos.device))
     _check(st)
     return diag
 

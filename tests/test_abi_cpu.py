@@ -185,3 +185,38 @@ def test_tuning_table(lib, tmp_path):
     nbody.tune_reset()
     assert nbody.tune_get("plain", 1 << 20) == nbody.tune_get("plain", (1 << 20) + 5)
     assert nbody.tune_get("comp", 5000) == before
+
+
+def test_jerk_entry_points_validate(lib):
+    n = 100
+    wsb = lib.nbody_workspace_bytes_jerk(n, 1)
+    assert wsb > lib.nbody_workspace_bytes_jerk(n, 0) > 0
+    assert lib.nbody_workspace_bytes_jerk(-1, 0) == 0 and lib.nbody_workspace_bytes_jerk(5, 3) == 0
+    pos, vel, mass = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
+    acc, jerk = ctypes.c_void_p(0x400000), ctypes.c_void_p(0x500000)
+    ws = ctypes.c_void_p(0x7000000)
+    ok = dict(pos=pos, vel=vel, mass=mass, n=n, eps=0.01, G=1.0, variant=1, acc=acc, jerk=jerk)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.nbody_accel_jerk(a["pos"], a["vel"], a["mass"], a["n"], a["eps"], a["G"], a["variant"],
+                                    a["acc"], a["jerk"], None, kw.get("ws", ws), kw.get("wsb", wsb), None)
+    assert call(n=-1) == nbody.EINVAL
+    assert call(variant=4) == nbody.ENOTSUP
+    assert call(eps=-1.0) == nbody.EINVAL
+    assert call(vel=None) == nbody.EINVAL
+    assert call(jerk=acc) == nbody.EINVAL          # outputs overlap
+    assert call(acc=vel) == nbody.EINVAL           # output overlaps an input
+    assert call(wsb=16) == nbody.EWORKSPACE
+    assert call(ws=ctypes.c_void_p(0x7000010)) == nbody.EWORKSPACE   # misaligned
+    assert call(n=0, pos=None) == nbody.OK
+
+    def step(**kw):
+        a = {**ok, "dt": 0.01, "steps": 3, **kw}
+        return lib.nbody_step_hermite(a["pos"], a["vel"], a["acc"], a["jerk"], None, a["mass"], a["n"], a["eps"],
+                                      a["G"], a["dt"], a["steps"], a["variant"], kw.get("diag"), ws, wsb, None)
+    assert step(steps=-1) == nbody.EINVAL
+    assert step(dt=math.nan) == nbody.EINVAL
+    assert step(jerk=vel) == nbody.EINVAL
+    assert step(diag=ctypes.c_void_p(0x100008)) == nbody.EINVAL
+    assert step(steps=0) == nbody.OK
