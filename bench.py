@@ -1,12 +1,15 @@
 """Benchmark of the direct-summation N-body hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--variant plain|comp] [--hermite] [--full-run] [--paper-run]
 
 A step is one kick-drift-kick leapfrog step of the whole path: kick and drift
 (FP64), the force evaluation (pack or double-single staging, the FP32 pair
 kernel, the j-split combine, the FP64 epilogue) and the closing kick fused
 with the FP64 energy/momentum diagnostics. Inputs are seeded synthetic
-Plummer spheres (or the cluster ensemble) already resident in HBM.
+Plummer spheres (or the cluster ensemble) already resident in HBM. With
+--hermite a step is one fourth-order Hermite step instead (FP64 predictor,
+the acceleration + jerk pair kernel, FP64 corrector and diagnostics).
 
 Prints one JSON line: throughput in G pair-interactions/s (N^2 pair
 evaluations per step, self pairs included, over the measured step time), the
@@ -31,8 +34,12 @@ if ROOT not in sys.path:
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
 FLOPS_PER_INTERACTION = 20        # the conventional count for one softened pair
+# Acceleration + jerk: the force's 20 plus the jerk's own FP32 work per pair
+# (relative velocity 3, d.w 5, alpha 2, w - alpha d 6, accumulation 6; an FMA
+# counts 2).
+FLOPS_PER_JERK_INTERACTION = 42
 DEFAULT_VARIANT = {"plummer_1k": "plain", "plummer_64k": "plain", "plummer_256k": "comp",
-                   "kroupa_1m": "comp", "ensemble_512": "comp"}
+                   "kroupa_1m": "comp", "ensemble_512": "comp", "plummer_102k": "plain"}
 
 # HBM bytes per force-kernel launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
 # passes, scaled by a 1 GiB copy (fetch x2.000, write x1.000), for the tuned
@@ -56,6 +63,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--hermite", action="store_true",
+                    help="time fourth-order Hermite steps (acceleration + jerk kernel) "
+                         "instead of kick-drift-kick steps")
+    ap.add_argument("--paper-run", action="store_true",
+                    help="the paper's representative run (N = 102,400, Hermite): time- and "
+                         "energy-to-solution for ten steps and for ten N-body time units")
     ap.add_argument("--full-run", action="store_true",
                     help="run the workload's whole step count and report time-to-solution, "
                          "energy/momentum drift and the final-state force error")
@@ -132,21 +145,109 @@ def full_run(name, variant, steps=None):
         plan.close()
 
 
-def cpu_baseline(pos, mass, eps, budget_s):
+PAPER_TIME_TO_SOLUTION_S = {"wormhole_n300_plus_host": 301.40, "cpu_2x_epyc_9124": 672.90}
+PAPER_ENERGY_TO_SOLUTION_KJ = {"wormhole_n300_plus_host": 71.56, "cpu_2x_epyc_9124": 128.89}
+
+
+def paper_run(variant, units=10.0, cpu_seconds=10.0):
+    """The paper's representative run (Section 5) on one GPU: N = 102,400
+    Plummer sphere, fourth-order Hermite with acceleration + jerk on the GPU
+    and the FP64 update on the GPU. The paper does not define its "time
+    cycle"; two readings are run: ten steps, and ten N-body time units at the
+    workload's step. Time-to-solution spans the host's initial conditions,
+    the upload, every force evaluation and update, and the download of the
+    final state; energy-to-solution covers the same span (GPU energy counter,
+    host RAPL when readable)."""
+    import torch
+
+    from oracle import cpu as ocpu
+    from oracle import oracle as orc
+    from paper_2509_19294_amd import ics, nbody
+    from paper_2509_19294_amd.energy import EnergyMeter
+
+    nbody.load()
+    dev = torch.device("cuda:0")
+    spec = dict(ics.WORKLOADS["plummer_102k"])
+    n, eps, dt = spec["n"], spec["eps"], spec["dt"]
+    # load the kernels' code objects once, outside the timed span
+    w = torch.zeros((256, 3), dtype=torch.float64, device=dev)
+    w[:, 0] = torch.arange(256, dtype=torch.float64, device=dev)
+    wm = torch.full((256,), 1.0 / 256, dtype=torch.float64, device=dev)
+    wa, wj, _ = nbody.accel_jerk(w, w.clone(), wm, eps, 1.0, variant)
+    nbody.step_hermite(w, w.clone(), wa, wj, wm, eps, 1.0, dt, 1, variant)
+    torch.cuda.synchronize()
+
+    readings = (("ten steps", spec["steps"]), (f"{units:g} time units", int(round(units / dt))))
+    for reading, steps in readings:
+        with EnergyMeter() as em:
+            t0 = time.perf_counter()
+            pos, vel, mass = ics.plummer(n, seed=spec["seed"])
+            t_ic = time.perf_counter() - t0
+            tp, tv, tm = (torch.from_numpy(x).to(dev) for x in (pos, vel, mass))
+            pot = torch.empty_like(tm)
+            acc, jerk, _ = nbody.accel_jerk(tp, tv, tm, eps, 1.0, variant, pot=pot)
+            d0 = nbody.step_hermite(tp, tv, acc, jerk, tm, eps, 1.0, 0.0, 1, variant, pot=pot)
+            diag = nbody.step_hermite(tp, tv, acc, jerk, tm, eps, 1.0, dt, steps, variant, pot=pot)
+            pf, vf = tp.cpu().numpy(), tv.cpu().numpy()
+            d = diag.cpu().numpy()
+            e0 = float(d0.cpu().numpy()[0, 2])
+            wall = time.perf_counter() - t0
+        energy = em.result()
+        de = np.abs(d[:, 2] - e0) / abs(e0)
+        out = {
+            "paper_run": "plummer_102k", "reading": reading, "variant": variant, "n": n, "eps": eps,
+            "dt": dt, "steps": steps, "force_jerk_evaluations": steps + 2,
+            "time_to_solution_s": round(wall, 3), "host_initial_conditions_s": round(t_ic, 3),
+            "G_pair_per_s": round(float(n) * n * (steps + 2) / wall / 1e9, 1),
+            "energy_drift_final": float(f"{de[-1]:.3e}"), "energy_drift_max": float(f"{de.max():.3e}"),
+            "nonfinite": int(d[:, 13].max()),
+            "energy_to_solution": energy,
+            "paper_time_to_solution_s": PAPER_TIME_TO_SOLUTION_S,
+            "paper_energy_to_solution_kJ": PAPER_ENERGY_TO_SOLUTION_KJ,
+        }
+        if reading == "ten steps":
+            # the final state's accelerations and jerks against the FP64 oracle
+            ta, tj, _ = nbody.accel_jerk(tp, tv, tm, eps, 1.0, variant)
+            tgt = orc.subsample_targets(n, 4096)
+            ra, rj, _ = ocpu.accel_jerk(pf, vf, mass, eps, targets=tgt)
+            ga, gj = ta.cpu().numpy()[tgt], tj.cpu().numpy()[tgt]
+            out["final_check"] = {
+                "targets": len(tgt), "acc_rel_rms": float(f"{orc.rel_rms(ga, ra):.3e}"),
+                "acc_paper_metric": float(f"{orc.paper_metric(ga, ra):.3e}"),
+                "jerk_rel_rms": float(f"{orc.rel_rms(gj, rj):.3e}"),
+                "jerk_paper_metric": float(f"{orc.paper_metric(gj, rj):.3e}"),
+            }
+            cb, _, _ = cpu_baseline(pos, mass, eps, cpu_seconds, vel=vel)
+            per_eval = float(n) * n / (cb["value"] * 1e9)
+            cb["time_to_solution_s_extrapolated"] = round(per_eval * (steps + 2), 1)
+            out["cpu_baseline"] = cb
+        print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(pos, mass, eps, budget_s, vel=None):
     """Time the FP64 C oracle (OpenMP over all host threads) on a bounded
     sample of the workload: whole force evaluations repeated, or, when one
     evaluation exceeds the budget, a strided subset of targets against all
-    sources. Returns the rate, the sample description and the oracle's values
-    on a strided subsample of at most 4096 targets (the accuracy gate)."""
+    sources. With ``vel`` the oracle evaluates accelerations and jerks.
+    Returns the rate, the sample description, the gate targets (a strided
+    subsample of at most 4096) and the oracle's values on them: (acc, pot)
+    or (acc, pot, jerk)."""
     from oracle import cpu as ocpu
     from oracle import oracle as orc
 
     ocpu.build(force=False)
     n = len(mass)
     threads = ocpu.max_threads()
+
+    def evaluate(targets=None):
+        if vel is None:
+            return ocpu.accel_pot(pos, mass, eps, targets=targets)
+        a, j, p = ocpu.accel_jerk(pos, vel, mass, eps, targets=targets)
+        return a, p, j
+
     probe = orc.subsample_targets(n, min(n, 64))
     t0 = time.perf_counter()
-    ocpu.accel_pot(pos, mass, eps, targets=probe)
+    evaluate(probe)
     rate = len(probe) * n / max(time.perf_counter() - t0, 1e-6)
     gate = orc.subsample_targets(n, 4096)
     full_s = float(n) * n / rate
@@ -154,27 +255,28 @@ def cpu_baseline(pos, mass, eps, budget_s):
         reps = int(max(1, min(50, round(budget_s / full_s))))
         t0 = time.perf_counter()
         for _ in range(reps):
-            acc, pot = ocpu.accel_pot(pos, mass, eps)
+            full = evaluate()
         el = time.perf_counter() - t0
         pairs = reps * float(n) * n
         sample = f"{reps} full evaluations of {n} x {n} pairs"
-        ref_a, ref_p = acc[gate], pot[gate]
+        refs = tuple(x[gate] for x in full)
     else:
         nt = int(min(n, max(256, budget_s * rate / n)))
         tgt = orc.subsample_targets(n, nt)
         t0 = time.perf_counter()
-        acc, pot = ocpu.accel_pot(pos, mass, eps, targets=tgt)
+        evaluate(tgt)
         el = time.perf_counter() - t0
         pairs = float(len(tgt)) * n
         sample = f"{len(tgt)} strided targets x {n} sources"
-        ref_a, ref_p = ocpu.accel_pot(pos, mass, eps, targets=gate)
+        refs = evaluate(gate)
+    what = "accelerations and potentials" if vel is None else "accelerations, jerks and potentials"
     return {
         "value": pairs / el / 1e9,
         "unit": "G pair-interactions/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"{sample} ({pairs:.3e} FP64 pairs in {el:.1f} s; C + OpenMP, {threads} threads)",
-    }, gate, ref_a, ref_p
+        "sample": f"{sample} ({pairs:.3e} FP64 pairs in {el:.1f} s; {what}; C + OpenMP, {threads} threads)",
+    }, gate, refs
 
 
 def copy_calibration(mib: int = 1024, reps: int = 5):
@@ -203,6 +305,9 @@ def main():
     if args.full_run:
         full_run(args.workload, args.variant or DEFAULT_VARIANT[args.workload])
         return
+    if args.paper_run:
+        paper_run(args.variant or "plain", cpu_seconds=args.cpu_seconds)
+        return
 
     import torch
 
@@ -227,22 +332,33 @@ def main():
         pairs_per_eval = float(n) * float(n)
     dt = spec["dt"]
 
+    hermite = args.hermite
+    if hermite and plan is not None:
+        print(json.dumps({"error": "--hermite runs on a single system, not the cluster ensemble"}))
+        sys.exit(2)
     tp = torch.from_numpy(pos).to(dev)
     tv = torch.from_numpy(vel).to(dev)
     tm = torch.from_numpy(mass).to(dev)
     pot = torch.empty_like(tm)
+    jerk = None
     if plan is not None:
         acc, _ = plan.accel(tp, tm, 1.0, pot=pot)
+    elif hermite:
+        acc, jerk, _ = nbody.accel_jerk(tp, tv, tm, eps, 1.0, variant, pot=pot)
     else:
         acc, _ = nbody.accel(tp, tm, eps, 1.0, variant, pot=pot)
     torch.cuda.synchronize()
     acc0 = acc.cpu().numpy()
     pot0 = pot.cpu().numpy()
+    jerk0 = jerk.cpu().numpy() if hermite else None
 
     diag = torch.empty((1, nbody.DIAG_LEN), dtype=torch.float64, device=dev)
 
     def one_step():
-        nbody.step(tp, tv, acc, tm, eps, 1.0, dt, 1, variant, plan=plan, diag=diag, pot=pot)
+        if hermite:
+            nbody.step_hermite(tp, tv, acc, jerk, tm, eps, 1.0, dt, 1, variant, diag=diag, pot=pot)
+        else:
+            nbody.step(tp, tv, acc, tm, eps, 1.0, dt, 1, variant, plan=plan, diag=diag, pot=pot)
 
     for _ in range(args.warmup):
         one_step()
@@ -275,16 +391,21 @@ def main():
         nbody.timing_enable(False)
 
     traffic = None
-    if plan is None:
+    if hermite:
+        traffic = MEASURED_TRAFFIC.get((name, variant, "jerk"))
+    elif plan is None:
         cfg, split = nbody.tune_get(variant, n)
         traffic = MEASURED_TRAFFIC.get((name, variant, cfg, split))
     ms_per_step = ms_total / args.steps
     value = pairs_per_eval / (ms_per_step * 1e-3) / 1e9
     kernel_avg_ms = kernel_ms / max(launches, 1)
-    achieved = FLOPS_PER_INTERACTION * pairs_per_eval / (kernel_avg_ms * 1e-3) / 1e12
+    flops = FLOPS_PER_JERK_INTERACTION if hermite else FLOPS_PER_INTERACTION
+    achieved = flops * pairs_per_eval / (kernel_avg_ms * 1e-3) / 1e12
 
     out = {
-        "metric": "G pair-interactions/s and % FP32 VALU peak at rel-RMS accel err <=1e-5 vs FP64",
+        "metric": ("G pair-interactions/s (acceleration + jerk) and % FP32 VALU peak at rel-RMS "
+                   "accel err <=1e-5 vs FP64" if hermite else
+                   "G pair-interactions/s and % FP32 VALU peak at rel-RMS accel err <=1e-5 vs FP64"),
         "value": round(value, 2),
         "unit": "G pair-interactions/s",
         "n_gpus": 1,
@@ -300,7 +421,8 @@ def main():
             "workload": f"{name}: " + (
                 f"{len(plan.eps)} Plummer clusters, N_total={n}" if plan is not None
                 else f"Plummer sphere N={n}" + (" Kroupa masses" if name == "kroupa_1m" else "")
-                + f", eps={eps}") + f", dt={dt}, one KDK step with diagnostics",
+                + f", eps={eps}") + f", dt={dt}, one "
+                + ("fourth-order Hermite" if hermite else "KDK") + " step with diagnostics",
             "variant": variant,
             "n": n,
             "pairs_per_step": pairs_per_eval,
@@ -314,7 +436,7 @@ def main():
             "traffic": traffic,
             "kernel_avg_ms": round(kernel_avg_ms, 4),
             "kernel_launches": launches,
-            "flops_per_interaction": FLOPS_PER_INTERACTION,
+            "flops_per_interaction": flops,
         },
     }
 
@@ -325,17 +447,20 @@ def main():
             # one mid-sized cluster's targets against its own sources
             k = int(np.argsort(ens.sizes)[len(ens.sizes) // 2])
             s, e = int(ens.offsets[k]), int(ens.offsets[k + 1])
-            cb, tgt, ref_a, ref_p = cpu_baseline(pos[s:e], mass[s:e], float(ens.eps[k]), args.cpu_seconds)
+            cb, tgt, refs = cpu_baseline(pos[s:e], mass[s:e], float(ens.eps[k]), args.cpu_seconds)
             a_s, p_s = acc0[s:e][tgt], pot0[s:e][tgt]
         else:
-            cb, tgt, ref_a, ref_p = cpu_baseline(pos, mass, eps, args.cpu_seconds)
+            cb, tgt, refs = cpu_baseline(pos, mass, eps, args.cpu_seconds, vel=vel if hermite else None)
             a_s, p_s = acc0[tgt], pot0[tgt]
+        ref_a, ref_p = refs[0], refs[1]
         out["cpu_baseline"] = cb
         acc_err = orc.rel_rms(a_s, ref_a)
         out["accuracy"] = {
             "acc_rel_rms": float(f"{acc_err:.3e}"),
             "acc_max_rel": float(f"{orc.max_rel(a_s, ref_a):.3e}"),
             "pot_rel_rms": float(f"{orc.rel_rms(p_s, ref_p):.3e}"),
+            **({"jerk_rel_rms": float(f"{orc.rel_rms(jerk0[tgt], refs[2]):.3e}"),
+                "jerk_paper_metric": float(f"{orc.paper_metric(jerk0[tgt], refs[2]):.3e}")} if hermite else {}),
             "targets": int(len(tgt)),
             "gate_rel_rms_1e-5": bool(acc_err <= 1e-5),
         }

@@ -1,0 +1,214 @@
+"""Energy-to-solution of a region of host code: GPU energy from the device's
+own energy accumulator, GPU power sampled in a background thread, host CPU
+package energy from the Linux powercap (RAPL) files when they are readable.
+
+The paper integrates card power sampled at about 1 Hz and reads CPU package
+energy through RAPL over the simulation's wall-clock span (Section 5). Here
+the GPU's cumulative energy counter gives the integral directly (no sampling
+error); the power samples (default 10 Hz) give the mean and the peak. Every
+source that is missing or not permitted is reported as None with a note,
+never guessed.
+
+    with EnergyMeter() as em:
+        run()
+    print(em.result())
+"""
+from __future__ import annotations
+
+import glob
+import os
+import threading
+import time
+
+
+def _amdsmi():
+    try:
+        import amdsmi
+    except Exception as e:  # pragma: no cover - depends on the machine
+        return None, f"amdsmi not importable: {e}"
+    return amdsmi, None
+
+
+def _torch_bus_id(device_index: int):
+    """PCI bus number of a torch device, or None."""
+    try:
+        import torch
+
+        props = torch.cuda.get_device_properties(device_index)
+        bus = getattr(props, "pci_bus_id", None)
+        return int(bus) if bus is not None else None
+    except Exception:
+        return None
+
+
+def _rapl_files():
+    """Top-level package energy files of the powercap interface."""
+    out = []
+    for d in sorted(glob.glob("/sys/class/powercap/*rapl*:[0-9]")):
+        f = os.path.join(d, "energy_uj")
+        m = os.path.join(d, "max_energy_range_uj")
+        if os.path.exists(f):
+            out.append((f, m))
+    return out
+
+
+def _read_int(path):
+    with open(path) as fh:
+        return int(fh.read().strip())
+
+
+class EnergyMeter:
+    """Context manager measuring GPU and host energy over its body."""
+
+    def __init__(self, device_index: int = 0, interval_s: float = 0.1):
+        self.device_index = device_index
+        self.interval_s = interval_s
+        self.notes: list[str] = []
+        self._smi = None
+        self._handle = None
+        self._samples: list[tuple[float, float]] = []
+        self._stop = threading.Event()
+        self._thread = None
+        self._e0 = self._e1 = None
+        self._rapl0 = self._rapl1 = None
+        self._t0 = self._t1 = None
+
+    # -- GPU ------------------------------------------------------------------
+    def _open_gpu(self):
+        smi, err = _amdsmi()
+        if smi is None:
+            self.notes.append(err)
+            return
+        try:
+            smi.amdsmi_init()
+        except Exception as e:
+            self.notes.append(f"amdsmi_init failed: {e}")
+            return
+        self._smi = smi
+        try:
+            handles = smi.amdsmi_get_processor_handles()
+        except Exception as e:
+            self.notes.append(f"no GPU handles: {e}")
+            return
+        bus = _torch_bus_id(self.device_index)
+        chosen = None
+        if bus is not None:
+            for h in handles:
+                try:
+                    bdf = smi.amdsmi_get_gpu_device_bdf(h)  # "dddd:bb:dd.f"
+                    if int(bdf.split(":")[1], 16) == bus:
+                        chosen = h
+                        break
+                except Exception:
+                    continue
+        if chosen is None and len(handles) == 1:
+            chosen = handles[0]
+        if chosen is None:
+            self.notes.append(f"could not match torch device {self.device_index} "
+                              f"(bus {bus}) among {len(handles)} GPUs")
+            return
+        self._handle = chosen
+
+    def _energy_j(self):
+        if self._handle is None:
+            return None
+        try:
+            r = self._smi.amdsmi_get_energy_count(self._handle)
+            return float(r["energy_accumulator"]) * float(r["counter_resolution"]) * 1e-6
+        except Exception as e:
+            self.notes.append(f"energy counter unreadable: {e}")
+            return None
+
+    def _power_w(self):
+        try:
+            info = self._smi.amdsmi_get_power_info(self._handle)
+        except Exception:
+            return None
+        for key in ("current_socket_power", "average_socket_power", "socket_power"):
+            v = info.get(key)
+            if isinstance(v, (int, float)) and v > 0:
+                return float(v)
+        return None
+
+    def _sampler(self):
+        while not self._stop.is_set():
+            p = self._power_w()
+            if p is not None:
+                self._samples.append((time.perf_counter(), p))
+            self._stop.wait(self.interval_s)
+
+    # -- host -----------------------------------------------------------------
+    def _rapl(self):
+        files = _rapl_files()
+        if not files:
+            return None
+        vals = []
+        for f, m in files:
+            try:
+                vals.append((_read_int(f), _read_int(m) if os.path.exists(m) else None))
+            except (PermissionError, OSError):
+                return None
+        return vals
+
+    # -- context --------------------------------------------------------------
+    def __enter__(self):
+        self._open_gpu()
+        self._rapl0 = self._rapl()
+        if self._rapl0 is None:
+            self.notes.append("host RAPL energy not readable (no powercap files or no permission)")
+        self._e0 = self._energy_j()
+        if self._handle is not None:
+            self._thread = threading.Thread(target=self._sampler, daemon=True)
+            self._thread.start()
+        self._t0 = time.perf_counter()
+        return self
+
+    def __exit__(self, *exc):
+        self._t1 = time.perf_counter()
+        self._e1 = self._energy_j()
+        self._rapl1 = self._rapl() if self._rapl0 is not None else None
+        self._stop.set()
+        if self._thread is not None:
+            self._thread.join()
+        if self._smi is not None:
+            try:
+                self._smi.amdsmi_shut_down()
+            except Exception:
+                pass
+        return False
+
+    def result(self) -> dict:
+        wall = (self._t1 - self._t0) if self._t1 is not None else None
+        gpu_j = None
+        if self._e0 is not None and self._e1 is not None:
+            gpu_j = self._e1 - self._e0
+            if gpu_j <= 0.0:
+                # the accumulator advances at the firmware's own interval
+                gpu_j = None
+                if "energy counter did not advance over the region" not in self.notes:
+                    self.notes.append("energy counter did not advance over the region")
+        host_j = None
+        if self._rapl0 is not None and self._rapl1 is not None:
+            host_j = 0.0
+            for (a, rng), (b, _) in zip(self._rapl0, self._rapl1):
+                d = b - a
+                if d < 0 and rng:
+                    d += rng
+                host_j += d * 1e-6
+        powers = [p for _, p in self._samples]
+        integ = None
+        if len(self._samples) >= 2:
+            integ = 0.0
+            for (ta, pa), (tb, pb) in zip(self._samples, self._samples[1:]):
+                integ += 0.5 * (pa + pb) * (tb - ta)
+        return {
+            "wall_s": None if wall is None else round(wall, 3),
+            "gpu_energy_j": None if gpu_j is None else round(gpu_j, 2),
+            "gpu_mean_power_w": None if (gpu_j is None or not wall) else round(gpu_j / wall, 1),
+            "gpu_power_samples": len(powers),
+            "gpu_peak_power_w": round(max(powers), 1) if powers else None,
+            # the paper's method: the trapezoid integral of the power samples
+            "gpu_energy_from_power_samples_j": None if integ is None else round(integ, 2),
+            "host_energy_j": None if host_j is None else round(host_j, 2),
+            "notes": self.notes,
+        }

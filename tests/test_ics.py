@@ -103,7 +103,8 @@ def test_ensemble_512_full():
 
 
 def test_workload_table():
-    assert set(ics.WORKLOADS) == {"plummer_1k", "plummer_64k", "plummer_256k", "ensemble_512", "kroupa_1m"}
+    assert set(ics.WORKLOADS) == {"plummer_1k", "plummer_64k", "plummer_256k", "ensemble_512", "kroupa_1m",
+                                  "plummer_102k"}
     pos, vel, mass, spec = ics.workload("plummer_1k")
     assert pos.shape == (1024, 3) and spec["eps"] == 0.01 and spec["dt"] == 1.0 / 128
     np.testing.assert_array_equal(pos, ics.plummer(1024, seed=0)[0])
