@@ -47,6 +47,8 @@ DEFAULT_VARIANT = {"plummer_1k": "plain", "plummer_64k": "plain", "plummer_256k"
 # whose dispatch differs reports null.
 MEASURED_TRAFFIC = {
     ("plummer_64k", "plain", 14, 32): 49328074,
+    # acceleration + jerk kernel (bench.py --hermite): shape 2, split 32
+    ("plummer_64k", "plain", "jerk", 2, 32): 99073280,
 }
 
 
@@ -392,7 +394,8 @@ def main():
 
     traffic = None
     if hermite:
-        traffic = MEASURED_TRAFFIC.get((name, variant, "jerk"))
+        cfg, split = nbody.tune_jerk_get(variant, n)
+        traffic = MEASURED_TRAFFIC.get((name, variant, "jerk", cfg, split))
     elif plan is None:
         cfg, split = nbody.tune_get(variant, n)
         traffic = MEASURED_TRAFFIC.get((name, variant, cfg, split))

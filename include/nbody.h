@@ -212,9 +212,24 @@ nbody_status nbody_step_hermite(double *pos, double *vel, double *acc, double *j
                                 int32_t n_steps, int32_t variant, double *diag, void *ws,
                                 size_t ws_bytes, void *stream);
 
+/* Shapes of the acceleration + jerk kernel, for the autotuner.
+ * nbody_tune_jerk_count: number of compiled shapes. nbody_tune_jerk_describe
+ * writes {K targets per lane, SW waves splitting the sources, targets per
+ * block} to out3 (host memory). nbody_tune_jerk_set forces cfg + 1000 * split
+ * (split 0 = the built-in rule) for every size of a variant; -1 returns to
+ * the built-in table. nbody_tune_jerk_get returns cfg + 1000 * split as used
+ * for n particles (-1 for invalid arguments). A forced split larger than the
+ * one a workspace was sized for makes the next call fail with
+ * NBODY_EWORKSPACE: size workspaces after forcing. nbody_tune_reset also
+ * clears the forced jerk shape. */
+int32_t nbody_tune_jerk_count(void);
+nbody_status nbody_tune_jerk_describe(int32_t cfg, int32_t *out3);
+nbody_status nbody_tune_jerk_set(int32_t variant, int32_t cfg);
+int32_t nbody_tune_jerk_get(int32_t variant, int64_t n);
+
 /* Kernel timing, for measurement. While enabled (on != 0), every
- * force-kernel launch made outside graph capture by nbody_accel, nbody_step
- * and nbody_accel_batched is bracketed by HIP events recorded on the stream
+ * force-kernel launch made outside graph capture by nbody_accel, nbody_step,
+ * nbody_accel_batched, nbody_accel_jerk and nbody_step_hermite is bracketed by HIP events recorded on the stream
  * it runs on (the bracket covers the pair kernel alone, not the pack before it
  * nor the split combine after it). nbody_timing_read waits for those events, returns the
  * number of bracketed launches and their summed duration in milliseconds, and

@@ -8,8 +8,9 @@ LDS or scalar source stream) with every grid j-split the workspace allows, on
 a seeded Plummer sphere, and keeps the fastest. For the batched kernel it
 times each mode on ensembles whose clusters all fall in one size class. The
 result is a tuning file for ``nbody_tune_load`` / ``NBODY_TUNE`` (lines
-``single <variant> <class> <cfg> <split>`` and ``batched <variant> <class>
-<mode>``) and a JSON record of every measurement.
+``single <variant> <class> <cfg> <split>``, ``batched <variant> <class>
+<mode>`` and ``jerk <variant> <class> <shape> <split>`` for the acceleration +
+jerk kernel) and a JSON record of every measurement.
 """
 from __future__ import annotations
 
@@ -78,6 +79,39 @@ def tune_single(variant, log2n, reps=5, splits=(1, 2, 4, 8, 16, 32), configs=Non
     return best, rows
 
 
+def tune_jerk(variant, log2n, reps=5, splits=(1, 2, 4, 8, 16, 32), log=None):
+    """Time every acceleration + jerk kernel shape with every grid j-split on
+    a Plummer sphere of 2^log2n particles; returns the fastest."""
+    import torch
+
+    n = 1 << log2n
+    pos, vel, mass = ics.plummer(n, seed=2000 + log2n)
+    tp, tv, tm = (torch.from_numpy(x).cuda() for x in (pos, vel, mass))
+    acc, jerk, pot = torch.empty_like(tp), torch.empty_like(tp), torch.empty_like(tm)
+    shapes = nbody.jerk_shapes()
+    if n >= (1 << 19):
+        reps = min(reps, 2)
+    best, rows = None, []
+    try:
+        for c, (k, sw, ib) in enumerate(shapes):
+            for sp in splits:
+                if sp > 1 and (math.ceil(n / ib) * sp > 64 * 1024 or n // sp < 1024 or sp * n > (1 << 23)):
+                    continue
+                nbody.tune_jerk_set(variant, c, sp)
+                ms = _time(lambda: nbody.accel_jerk(tp, tv, tm, 0.01, 1.0, variant, acc=acc, jerk=jerk,
+                                                    pot=pot), reps)
+                rate = float(n) * n / (ms * 1e-3) / 1e9
+                rows.append({"kernel": "jerk", "variant": variant, "log2n": log2n, "cfg": c, "k": k, "sw": sw,
+                             "split": sp, "ms": round(ms, 4), "G_int_per_s": round(rate, 1)})
+                if log:
+                    log(rows[-1])
+                if best is None or ms < best[2]:
+                    best = (c, sp, ms)
+    finally:
+        nbody.tune_jerk_set(variant, -1)
+    return best, rows
+
+
 def _class_ensemble(c, k, seed):
     rng = np.random.default_rng(seed)
     sizes = rng.integers(1 << c, (1 << (c + 1)) - 1, size=k, endpoint=True)
@@ -133,6 +167,7 @@ def main():
     ap.add_argument("--variants", default="plain,comp")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--no-jerk", action="store_true")
     args = ap.parse_args()
     nbody.load()
     nbody.tune_reset()
@@ -149,6 +184,10 @@ def main():
             (cfg, sp, ms), _ = tune_single(variant, c, log=log)
             lines.append(f"single {v} {c} {cfg} {sp}")
             print(f"# best {variant} 2^{c}: cfg {cfg} split {sp} {ms:.4f} ms", flush=True)
+        for c in ([] if args.no_jerk else range(args.min_log2, args.max_log2 + 1)):
+            (cfg, sp, ms), _ = tune_jerk(variant, c, log=log)
+            lines.append(f"jerk {v} {c} {cfg} {sp}")
+            print(f"# best jerk {variant} 2^{c}: shape {cfg} split {sp} {ms:.4f} ms", flush=True)
         if not args.no_batched:
             for c in range(8, 14):
                 (mode, ms), _ = tune_batched(variant, c, log=log)

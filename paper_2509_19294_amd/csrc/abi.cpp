@@ -114,6 +114,15 @@ const SingleTune kTuned[2][11] = {
     {{5, 4}, {5, 8}, {5, 8}, {0, 16}, {15, 16}, {9, 32}, {9, 32}, {9, 32}, {9, 32}, {15, 2}, {9, 2}},
 };
 const int kTunedBatched[2][6] = {{8, 4, 4, 4, 4, 4}, {1, 4, 4, 4, 4, 4}};
+// Acceleration + jerk kernel: {shape, split} per size class 10..20, measured
+// on MI355X by the same autotuner (Plummer spheres of 2^c particles,
+// eps = 0.01; split 0 would select the rule of jerk_default_split).
+const SingleTune kTunedJerk[2][11] = {
+    {{2, 1}, {2, 2}, {2, 4}, {2, 8}, {2, 16}, {2, 32}, {2, 32}, {1, 32}, {1, 32}, {2, 8}, {1, 8}},
+    {{2, 1}, {2, 2}, {2, 4}, {2, 8}, {2, 16}, {2, 16}, {2, 16}, {2, 32}, {1, 32}, {0, 16}, {2, 4}},
+};
+SingleTune g_jerk[2][kClasses];
+int g_jerk_forced[2] = {-1, -1};
 
 void tune_defaults() {
   for (int v = 0; v < 2; ++v) {
@@ -123,7 +132,9 @@ void tune_defaults() {
       const int bc = c < 8 ? 0 : (c > 13 ? 5 : c - 8);
       g_batched[v][c] = kTunedBatched[v][bc];
       g_forced[v][c] = -1;
+      g_jerk[v][c] = kTunedJerk[v][tc];
     }
+    g_jerk_forced[v] = -1;
   }
 }
 
@@ -154,6 +165,12 @@ nbody_status tune_load_locked(const char *path) {
         return fail(NBODY_EINVAL, "tuning file '%s' line %d: bad batched entry", path, lineno);
       }
       g_batched[v][c] = a;
+    } else if (std::strcmp(kind, "jerk") == 0) {
+      if (a < 0 || a >= nb::jerk_shape_count() || b < 0 || b > nb::kMaxSplit) {
+        std::fclose(f);
+        return fail(NBODY_EINVAL, "tuning file '%s' line %d: bad jerk entry", path, lineno);
+      }
+      g_jerk[v][c] = SingleTune{a, b};
     } else {
       std::fclose(f);
       return fail(NBODY_EINVAL, "tuning file '%s' line %d: unknown kind", path, lineno);
@@ -180,6 +197,18 @@ SingleTune single_tune(int32_t variant, int64_t n) {
     const int f = g_forced[variant][c];
     t = SingleTune{f % 1000, f / 1000 > 0 ? f / 1000 : 1};
   }
+  return t;
+}
+
+// Shape and split of the acceleration + jerk kernel for n particles.
+SingleTune jerk_tune(int32_t variant, int64_t n) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_init_locked();
+  SingleTune t = g_jerk[variant][size_class(n)];
+  if (g_jerk_forced[variant] >= 0) t = SingleTune{g_jerk_forced[variant] % 1000, g_jerk_forced[variant] / 1000};
+  if (t.split <= 0) t.split = nb::jerk_default_split(n, t.cfg);
+  // the partial buffer holds at most kPartCap entries
+  while (t.split > 1 && static_cast<int64_t>(t.split) * n > nb::kPartCap) t.split /= 2;
   return t;
 }
 
@@ -284,7 +313,7 @@ JerkLayout jerk_layout(int64_t n, int32_t variant) {
   L.packed = off;
   off += align_up(static_cast<size_t>(nb::padded(n)) * (comp ? 3 : 2) * sizeof(float4));
   L.part = off;
-  const int split = nb::jerk_split(n);
+  const int split = jerk_tune(variant, n).split;
   off += align_up(split > 1 ? static_cast<size_t>(split) * un * (comp ? 4 : 2) * sizeof(float4) : 0);
   L.xp = off;
   off += align_up(un * 3 * sizeof(double));
@@ -313,8 +342,9 @@ hipError_t enqueue_accel_jerk(const double *pos, const double *vel, const double
   float4 *packed = at<float4>(ws, L.packed);
   hipError_t e = nb::launch_pack_jerk(pos, vel, mass, n, comp, packed, st);
   if (e != hipSuccess) return e;
+  const SingleTune t = jerk_tune(variant, n);
   hipEvent_t stop = timing_begin(st);
-  return nb::launch_pair_jerk(comp, packed, mass, n, eps, G, nb::jerk_split(n), acc, jerk, pot,
+  return nb::launch_pair_jerk(t.cfg, comp, packed, mass, n, eps, G, t.split, acc, jerk, pot,
                               at<float4>(ws, L.part), st, stop);
 }
 
@@ -847,6 +877,40 @@ nbody_status nbody_timing_read(int64_t *launches, double *total_ms) {
   *launches = count;
   *total_ms = sum;
   return NBODY_OK;
+}
+
+int32_t nbody_tune_jerk_count(void) { return nb::jerk_shape_count(); }
+
+nbody_status nbody_tune_jerk_describe(int32_t cfg, int32_t *out3) {
+  g_err.clear();
+  if (!out3) return fail(NBODY_EINVAL, "out3 is NULL");
+  if (cfg < 0 || cfg >= nb::jerk_shape_count()) return fail(NBODY_EINVAL, "no jerk shape %d", cfg);
+  int k = 0, sw = 0;
+  nb::jerk_shape(cfg, &k, &sw);
+  out3[0] = k;
+  out3[1] = sw;
+  out3[2] = nb::jerk_targets_per_block(cfg);
+  return NBODY_OK;
+}
+
+nbody_status nbody_tune_jerk_set(int32_t variant, int32_t cfg) {
+  g_err.clear();
+  if (!valid_variant(variant)) return fail(NBODY_ENOTSUP, "unknown variant %d", variant);
+  if (cfg != -1) {
+    const int c = cfg % 1000, sp = cfg / 1000;
+    if (cfg < 0 || c >= nb::jerk_shape_count() || sp > nb::kMaxSplit)
+      return fail(NBODY_EINVAL, "bad jerk configuration %d", cfg);
+  }
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_init_locked();
+  g_jerk_forced[variant] = cfg;
+  return NBODY_OK;
+}
+
+int32_t nbody_tune_jerk_get(int32_t variant, int64_t n) {
+  if (!valid_variant(variant) || n < 0) return -1;
+  const SingleTune t = jerk_tune(variant, n);
+  return t.cfg + 1000 * t.split;
 }
 
 nbody_status nbody_tune_reset(void) {

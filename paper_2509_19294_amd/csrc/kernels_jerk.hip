@@ -6,8 +6,10 @@
 //   jerk_i = G sum_{j != i} m_j [w q^{-3/2} - 3 (d.w) d q^{-5/2}],
 //   d = x_j - x_i, w = v_j - v_i, q = |d|^2 + eps^2.
 // Per pair, on top of the force's 13 FP32 operations and one v_rsq_f32: the
-// relative velocity (3), d.w (3), alpha = 3 (d.w) rho^2 (2), t = w - alpha d
-// (3) and jerk += m rho^3 t (3).
+// relative velocity (3), d.w (3), s beta = s (d.w) rho^2 (2), J1 += s w (3)
+// and J2 += s beta d (3), with s = m rho^3; the jerk is J1 - 3 J2, formed
+// once per target (two accumulators instead of one keep the factor 3, a
+// literal operand, out of the pair loop).
 //
 // The kernel follows the scalar-stream layout of the force kernel: each wave
 // streams its sources from a zero-padded packed array with scalar loads
@@ -75,7 +77,8 @@ __global__ __launch_bounds__(256) void pair_jerk_kernel(const float4 *__restrict
   constexpr int G4 = 4;             // sources per group
   constexpr int STEP = SW * G4;     // stride between a wave's groups
   constexpr int TJ = 256;           // sources per wave per tile
-  constexpr int NQ = 8;             // accumulated quantities: a(3), phi, jerk(3), pad
+  // accumulated quantities: a (3), phi, J1 = sum s w (3), J2 = sum s beta d (3)
+  constexpr int NQ = 10;
   constexpr int OW = COMP ? 4 : 2;  // float4 words per partial entry
   static_assert(NW % SW == 0, "bad shape");
   __shared__ float X[(SW > 1) ? (SW - 1) * NG * 64 * K * NQ * (COMP ? 2 : 1) : 1];
@@ -169,21 +172,24 @@ __global__ __launch_bounds__(256) void pair_jerk_kernel(const float4 *__restrict
           float rv = dx * wx;
           rv = fmaf(dy, wy, rv);
           rv = fmaf(dz, wz, rv);
-          const float alpha = (rv * rho2) * 3.0f;
+          const float sb = s * (rv * rho2);
           p[k][0] = fmaf(s, dx, p[k][0]);
           p[k][1] = fmaf(s, dy, p[k][1]);
           p[k][2] = fmaf(s, dz, p[k][2]);
           p[k][3] += mr;
-          p[k][4] = fmaf(s, fmaf(-alpha, dx, wx), p[k][4]);
-          p[k][5] = fmaf(s, fmaf(-alpha, dy, wy), p[k][5]);
-          p[k][6] = fmaf(s, fmaf(-alpha, dz, wz), p[k][6]);
+          p[k][4] = fmaf(s, wx, p[k][4]);
+          p[k][5] = fmaf(s, wy, p[k][5]);
+          p[k][6] = fmaf(s, wz, p[k][6]);
+          p[k][7] = fmaf(sb, dx, p[k][7]);
+          p[k][8] = fmaf(sb, dy, p[k][8]);
+          p[k][9] = fmaf(sb, dz, p[k][9]);
         }
       }
     }
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-      for (int c = 0; c < 7; ++c) {
+      for (int c = 0; c < NQ; ++c) {
         if constexpr (COMP) {
           float hs, he;
           two_sum(ah[k][c], p[k][c], hs, he);
@@ -203,7 +209,7 @@ __global__ __launch_bounds__(256) void pair_jerk_kernel(const float4 *__restrict
 #pragma unroll
       for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int c = 0; c < 7; ++c) {
+        for (int c = 0; c < NQ; ++c) {
           X[(wj - 1) * SLOT + base + (k * NQ + c) * CW] = ah[k][c];
           if constexpr (COMP) X[(wj - 1) * SLOT + base + (k * NQ + c) * CW + 1] = al[k][c];
         }
@@ -214,7 +220,7 @@ __global__ __launch_bounds__(256) void pair_jerk_kernel(const float4 *__restrict
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
-          for (int c = 0; c < 7; ++c) {
+          for (int c = 0; c < NQ; ++c) {
             const float oh = X[(w - 1) * SLOT + base + (k * NQ + c) * CW];
             if constexpr (COMP) {
               const float ol = X[(w - 1) * SLOT + base + (k * NQ + c) * CW + 1];
@@ -235,25 +241,42 @@ __global__ __launch_bounds__(256) void pair_jerk_kernel(const float4 *__restrict
     const int64_t i = iidx[k];
     if (i >= i1) continue;
     if (o.part) {
+      // fold jerk = J1 - 3 J2 into one partial (exactly for the hi/lo form:
+      // the product's rounding error from an FMA, the sum's from TwoSum)
+      float jh[3], jl[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float pr = -3.0f * ah[k][7 + c];
+        if constexpr (COMP) {
+          const float pe = fmaf(-3.0f, ah[k][7 + c], -pr);
+          float hs, he;
+          two_sum(ah[k][4 + c], pr, hs, he);
+          jh[c] = hs;
+          jl[c] = fmaf(-3.0f, al[k][7 + c], al[k][4 + c]) + (pe + he);
+        } else {
+          jh[c] = fmaf(-3.0f, ah[k][7 + c], ah[k][4 + c]);
+          jl[c] = 0.f;
+        }
+      }
       float4 *P = o.part + (static_cast<int64_t>(blockIdx.y) * o.n + i) * OW;
       P[0] = make_float4(ah[k][0], ah[k][1], ah[k][2], ah[k][3]);
-      P[1] = make_float4(ah[k][4], ah[k][5], ah[k][6], 0.f);
+      P[1] = make_float4(jh[0], jh[1], jh[2], 0.f);
       if constexpr (COMP) {
         P[2] = make_float4(al[k][0], al[k][1], al[k][2], al[k][3]);
-        P[3] = make_float4(al[k][4], al[k][5], al[k][6], 0.f);
+        P[3] = make_float4(jl[0], jl[1], jl[2], 0.f);
       }
     } else {
-      double sum[7];
+      double sum[NQ];
 #pragma unroll
-      for (int c = 0; c < 7; ++c)
+      for (int c = 0; c < NQ; ++c)
         sum[c] = COMP ? static_cast<double>(ah[k][c]) + static_cast<double>(al[k][c])
                       : static_cast<double>(ah[k][c]);
       o.acc[3 * i] = o.G * sum[0];
       o.acc[3 * i + 1] = o.G * sum[1];
       o.acc[3 * i + 2] = o.G * sum[2];
-      o.jerk[3 * i] = o.G * sum[4];
-      o.jerk[3 * i + 1] = o.G * sum[5];
-      o.jerk[3 * i + 2] = o.G * sum[6];
+      o.jerk[3 * i] = o.G * (sum[4] - 3.0 * sum[7]);
+      o.jerk[3 * i + 1] = o.G * (sum[5] - 3.0 * sum[8]);
+      o.jerk[3 * i + 2] = o.G * (sum[6] - 3.0 * sum[9]);
       if (o.pot) {
         const double self = EPS0 ? 0.0 : static_cast<double>(self_term(mi[k], eps2f));
         o.pot[i] = -o.G * (sum[3] - self);
@@ -341,6 +364,29 @@ hipError_t launch_jerk_t(bool comp, bool eps0, dim3 grid, const float4 *packed, 
   return hipGetLastError();
 }
 
+// Compiled shapes: K targets per lane, SW of the block's four waves splitting
+// the sources of one target group.
+struct JerkShape {
+  int k, sw;
+};
+constexpr JerkShape kJerkShapes[] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2}, {2, 4}, {4, 1}, {4, 2}};
+constexpr int kJerkShapeCount = static_cast<int>(sizeof(kJerkShapes) / sizeof(kJerkShapes[0]));
+
+hipError_t launch_jerk_shape(int cfg, bool comp, bool eps0, dim3 grid, const float4 *packed, int64_t n,
+                             float eps2f, int64_t split_len, const JerkOut &o, hipStream_t st) {
+  switch (cfg) {
+    case 0: return launch_jerk_t<1, 1>(comp, eps0, grid, packed, n, eps2f, split_len, o, st);
+    case 1: return launch_jerk_t<1, 2>(comp, eps0, grid, packed, n, eps2f, split_len, o, st);
+    case 2: return launch_jerk_t<1, 4>(comp, eps0, grid, packed, n, eps2f, split_len, o, st);
+    case 3: return launch_jerk_t<2, 1>(comp, eps0, grid, packed, n, eps2f, split_len, o, st);
+    case 4: return launch_jerk_t<2, 2>(comp, eps0, grid, packed, n, eps2f, split_len, o, st);
+    case 5: return launch_jerk_t<2, 4>(comp, eps0, grid, packed, n, eps2f, split_len, o, st);
+    case 6: return launch_jerk_t<4, 1>(comp, eps0, grid, packed, n, eps2f, split_len, o, st);
+    case 7: return launch_jerk_t<4, 2>(comp, eps0, grid, packed, n, eps2f, split_len, o, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 unsigned elementwise_grid(int64_t n3) {
   int64_t b = (n3 + 255) / 256;
   if (b > 8192) b = 8192;
@@ -349,10 +395,23 @@ unsigned elementwise_grid(int64_t n3) {
 
 }  // namespace
 
-int jerk_split(int64_t n) {
-  // Targets per block are 128 (K = 1, two waves splitting the sources); aim
-  // for about 8192 blocks, within the partial buffer's bound.
-  const int64_t blocks = (n + 127) / 128;
+int jerk_shape_count() { return kJerkShapeCount; }
+
+int jerk_targets_per_block(int cfg) {
+  if (cfg < 0 || cfg >= kJerkShapeCount) return 0;
+  return (4 / kJerkShapes[cfg].sw) * 64 * kJerkShapes[cfg].k;
+}
+
+void jerk_shape(int cfg, int *k, int *sw) {
+  *k = kJerkShapes[cfg].k;
+  *sw = kJerkShapes[cfg].sw;
+}
+
+int jerk_default_split(int64_t n, int cfg) {
+  // Aim for about 8192 blocks, each split keeping at least 1024 sources,
+  // within the partial buffer's bound.
+  const int ib = jerk_targets_per_block(cfg);
+  const int64_t blocks = (n + ib - 1) / ib;
   int split = 1;
   while (split < kMaxSplit && blocks * split < 8192 && n / (split * 2) >= 1024 &&
          static_cast<int64_t>(split * 2) * n <= kPartCap)
@@ -369,12 +428,13 @@ hipError_t launch_pack_jerk(const double *pos, const double *vel, const double *
   return hipGetLastError();
 }
 
-hipError_t launch_pair_jerk(bool comp, const float4 *packed, const double *mass, int64_t n,
+hipError_t launch_pair_jerk(int cfg, bool comp, const float4 *packed, const double *mass, int64_t n,
                             double eps, double G, int split, double *acc, double *jerk,
                             double *pot, float4 *part, hipStream_t stream, hipEvent_t after_pair) {
   if (n <= 0) return hipSuccess;
-  constexpr int K = 1, SW = 2, IB = (4 / SW) * 64 * K;
-  const int64_t nblk = (n + IB - 1) / IB;
+  const int ib = jerk_targets_per_block(cfg);
+  if (ib == 0 || split > kMaxSplit) return hipErrorInvalidValue;
+  const int64_t nblk = (n + ib - 1) / ib;
   if (split < 1) split = 1;
   int64_t split_len = (n + split - 1) / split;
   split_len = (split_len + kPad - 1) / kPad * kPad;
@@ -391,7 +451,7 @@ hipError_t launch_pair_jerk(bool comp, const float4 *packed, const double *mass,
     o.pot = pot;
   }
   dim3 grid(static_cast<unsigned>(nblk), static_cast<unsigned>(split));
-  hipError_t e = launch_jerk_t<K, SW>(comp, eps0, grid, packed, n, eps2f, split_len, o, stream);
+  hipError_t e = launch_jerk_shape(cfg, comp, eps0, grid, packed, n, eps2f, split_len, o, stream);
   if (e == hipSuccess && after_pair) e = hipEventRecord(after_pair, stream);
   if (e != hipSuccess || split == 1) return e;
   const unsigned cb = static_cast<unsigned>((n + 255) / 256);

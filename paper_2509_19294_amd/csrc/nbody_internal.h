@@ -103,10 +103,15 @@ int batched_grid(bool comp, int mode);  // persistent grid (blocks) for the curr
 // Acceleration + jerk (kernels_jerk.hip). Packed sources hold 2 (plain) or
 // 3 (compensated) float4 per particle, padded(n) particles; partials hold
 // split x n x (2 or 4) float4.
-int jerk_split(int64_t n);
+// Compiled kernel shapes: cfg in [0, jerk_shape_count()); K targets per
+// lane and SW waves splitting the sources of a target group.
+int jerk_shape_count();
+void jerk_shape(int cfg, int *k, int *sw);
+int jerk_targets_per_block(int cfg);
+int jerk_default_split(int64_t n, int cfg);
 hipError_t launch_pack_jerk(const double *pos, const double *vel, const double *mass, int64_t n,
                             bool comp, float4 *packed, hipStream_t stream);
-hipError_t launch_pair_jerk(bool comp, const float4 *packed, const double *mass, int64_t n,
+hipError_t launch_pair_jerk(int cfg, bool comp, const float4 *packed, const double *mass, int64_t n,
                             double eps, double G, int split, double *acc, double *jerk,
                             double *pot, float4 *part, hipStream_t stream,
                             hipEvent_t after_pair = nullptr);

@@ -76,6 +76,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                        sz, c_dp]),
             "nbody_step_hermite": (i32, [c_dp, c_dp, c_dp, c_dp, c_dp, c_dp, i64, dbl, dbl, dbl, i32,
                                          i32, c_dp, c_dp, sz, c_dp]),
+            "nbody_tune_jerk_count": (i32, []),
+            "nbody_tune_jerk_describe": (i32, [i32, ctypes.POINTER(i32)]),
+            "nbody_tune_jerk_set": (i32, [i32, i32]),
+            "nbody_tune_jerk_get": (i32, [i32, i64]),
             "nbody_timing_enable": (i32, [i32]),
             "nbody_timing_read": (i32, [ctypes.POINTER(i64), ctypes.POINTER(dbl)]),
         }
@@ -369,6 +373,30 @@ def tune_set(variant, size_class: int, cfg: int, split: int = 1):
 def tune_get(variant, n: int):
     code = int(load().nbody_tune_get(_variant(variant), int(n)))
     return code % 1000, max(code // 1000, 1)
+
+
+def jerk_shapes():
+    """List of (K, SW, targets per block) of the compiled acceleration + jerk
+    kernel shapes."""
+    lib = load()
+    buf = (ctypes.c_int32 * 3)()
+    out = []
+    for c in range(lib.nbody_tune_jerk_count()):
+        _check(lib.nbody_tune_jerk_describe(c, buf))
+        out.append(tuple(buf))
+    return out
+
+
+def tune_jerk_set(variant, cfg: int, split: int = 0):
+    """Force jerk-kernel shape ``cfg`` with grid j-split ``split`` (0 = the
+    built-in rule) for every size; cfg = -1 restores the table."""
+    code = -1 if cfg < 0 else cfg + 1000 * split
+    _check(load().nbody_tune_jerk_set(_variant(variant), int(code)))
+
+
+def tune_jerk_get(variant, n: int):
+    code = int(load().nbody_tune_jerk_get(_variant(variant), int(n)))
+    return code % 1000, code // 1000
 
 
 def tune_load(path: str):

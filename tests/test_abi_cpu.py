@@ -220,3 +220,46 @@ def test_jerk_entry_points_validate(lib):
     assert step(jerk=vel) == nbody.EINVAL
     assert step(diag=ctypes.c_void_p(0x100008)) == nbody.EINVAL
     assert step(steps=0) == nbody.OK
+
+
+def test_jerk_shapes_and_forcing(lib, tmp_path):
+    shapes = nbody.jerk_shapes()
+    assert len(shapes) == lib.nbody_tune_jerk_count() >= 4
+    for k, sw, ib in shapes:
+        assert k in (1, 2, 4) and sw in (1, 2, 4) and ib == (4 // sw) * 64 * k
+    buf = (ctypes.c_int32 * 3)()
+    assert lib.nbody_tune_jerk_describe(len(shapes), buf) == nbody.EINVAL
+    assert lib.nbody_tune_jerk_describe(0, None) == nbody.EINVAL
+    assert lib.nbody_tune_jerk_set(0, len(shapes)) == nbody.EINVAL
+    assert lib.nbody_tune_jerk_set(0, 33 * 1000) == nbody.EINVAL
+    assert lib.nbody_tune_jerk_set(7, 0) == nbody.ENOTSUP
+    assert lib.nbody_tune_jerk_get(0, -1) == -1
+    n = 65536
+    before = nbody.tune_jerk_get("plain", n)
+    assert before[1] >= 1
+    # a forced split resizes the workspace the next call needs
+    nbody.tune_jerk_set("plain", 0, 1)
+    assert nbody.tune_jerk_get("plain", n) == (0, 1)
+    small = lib.nbody_workspace_bytes_jerk(n, 0)
+    nbody.tune_jerk_set("plain", 0, 16)
+    assert nbody.tune_jerk_get("plain", n) == (0, 16)
+    assert lib.nbody_workspace_bytes_jerk(n, 0) == small + 16 * n * 2 * 16
+    # split 0 = the built-in rule; the partial buffer bound caps any split
+    nbody.tune_jerk_set("plain", 3, 0)
+    assert nbody.tune_jerk_get("plain", n)[0] == 3 and nbody.tune_jerk_get("plain", n)[1] >= 1
+    nbody.tune_jerk_set("plain", 0, 32)
+    assert nbody.tune_jerk_get("plain", 1 << 20) == (0, 8)
+    nbody.tune_jerk_set("plain", -1)
+    assert nbody.tune_jerk_get("plain", n) == before
+    # tuning files carry jerk lines; reset restores the table
+    f = tmp_path / "j.txt"
+    f.write_text("jerk 1 16 4 2\n")
+    nbody.tune_load(str(f))
+    assert nbody.tune_jerk_get("comp", n) == (4, 2)
+    bad = tmp_path / "jb.txt"
+    bad.write_text("jerk 1 16 99 2\n")
+    with pytest.raises(nbody.NbodyError):
+        nbody.tune_load(str(bad))
+    nbody.tune_jerk_set("comp", 2, 4)
+    nbody.tune_reset()
+    assert nbody.tune_jerk_get("comp", n) != (2, 4) and nbody.tune_jerk_get("comp", n) != (4, 2)

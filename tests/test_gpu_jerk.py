@@ -32,6 +32,9 @@ DEV = "cuda:0"
 def _setup():
     ocpu.build(force=False)
     nbody.load()
+    nbody.tune_reset()
+    yield
+    nbody.tune_reset()
 
 
 def T(x):
@@ -93,6 +96,27 @@ def test_sizes(variant, n, eps):
     check((a, j, p), references(pos, vel, mass, eps, variant), (variant, n, eps))
     a2, j2, p2 = gpu_accel_jerk(pos, vel, mass, eps, variant)
     assert np.array_equal(a, a2) and np.array_equal(j, j2) and np.array_equal(p, p2)
+
+
+@pytest.mark.parametrize("variant", ["plain", "comp"])
+@pytest.mark.parametrize("eps", [0.01, 0.0])
+def test_every_shape_and_split(variant, eps):
+    """Every compiled kernel shape, with and without a grid j-split, on a
+    ragged size; each result is bitwise reproducible."""
+    n = 3001
+    pos, vel, mass = ics.plummer(n, seed=77)
+    refs = references(pos, vel, mass, eps, variant)
+    try:
+        for cfg in range(len(nbody.jerk_shapes())):
+            for split in (1, 3, 4):
+                nbody.tune_jerk_set(variant, cfg, split)
+                assert nbody.tune_jerk_get(variant, n) == (cfg, split)
+                got = gpu_accel_jerk(pos, vel, mass, eps, variant)
+                check(got, refs, (variant, eps, cfg, split))
+                again = gpu_accel_jerk(pos, vel, mass, eps, variant)
+                assert all(np.array_equal(x, y) for x, y in zip(got, again)), (cfg, split)
+    finally:
+        nbody.tune_jerk_set(variant, -1)
 
 
 def test_jerk_boosted_and_shifted_frame():
