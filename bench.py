@@ -247,18 +247,30 @@ def cpu_baseline(pos, mass, eps, budget_s, vel=None):
         a, j, p = ocpu.accel_jerk(pos, vel, mass, eps, targets=targets)
         return a, p, j
 
-    probe = orc.subsample_targets(n, min(n, 64))
-    t0 = time.perf_counter()
-    evaluate(probe)
-    rate = len(probe) * n / max(time.perf_counter() - t0, 1e-6)
+    # rate probe: strided targets against all sources, grown until it takes
+    # a measurable time (thread start-up dominates tiny probes)
+    nprobe = min(n, 64)
+    while True:
+        probe = orc.subsample_targets(n, nprobe)
+        t0 = time.perf_counter()
+        evaluate(probe)
+        dt_probe = time.perf_counter() - t0
+        if dt_probe >= 0.25 or nprobe >= n:
+            break
+        nprobe = min(n, nprobe * 4)
+    rate = len(probe) * n / max(dt_probe, 1e-6)
     gate = orc.subsample_targets(n, 4096)
     full_s = float(n) * n / rate
-    if full_s <= budget_s:
-        reps = int(max(1, min(50, round(budget_s / full_s))))
+    if full_s <= 0.5 * budget_s:
+        # whole evaluations, repeated until the budget is spent
+        reps = 0
         t0 = time.perf_counter()
-        for _ in range(reps):
+        while True:
             full = evaluate()
-        el = time.perf_counter() - t0
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or reps >= 1000:
+                break
         pairs = reps * float(n) * n
         sample = f"{reps} full evaluations of {n} x {n} pairs"
         refs = tuple(x[gate] for x in full)
