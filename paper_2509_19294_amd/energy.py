@@ -57,6 +57,39 @@ def _read_int(path):
         return int(fh.read().strip())
 
 
+def _open_handle(device_index: int):
+    """(amdsmi module, processor handle, notes) for a torch device; the
+    handle is None (with a note) when it cannot be found."""
+    notes = []
+    smi, err = _amdsmi()
+    if smi is None:
+        return None, None, [err]
+    try:
+        smi.amdsmi_init()
+    except Exception as e:
+        return None, None, [f"amdsmi_init failed: {e}"]
+    try:
+        handles = smi.amdsmi_get_processor_handles()
+    except Exception as e:
+        return smi, None, [f"no GPU handles: {e}"]
+    bus = _torch_bus_id(device_index)
+    chosen = None
+    if bus is not None:
+        for h in handles:
+            try:
+                bdf = smi.amdsmi_get_gpu_device_bdf(h)  # "dddd:bb:dd.f"
+                if int(bdf.split(":")[1], 16) == bus:
+                    chosen = h
+                    break
+            except Exception:
+                continue
+    if chosen is None and len(handles) == 1:
+        chosen = handles[0]
+    if chosen is None:
+        notes.append(f"could not match torch device {device_index} (bus {bus}) among {len(handles)} GPUs")
+    return smi, chosen, notes
+
+
 class EnergyMeter:
     """Context manager measuring GPU and host energy over its body."""
 
@@ -75,39 +108,8 @@ class EnergyMeter:
 
     # -- GPU ------------------------------------------------------------------
     def _open_gpu(self):
-        smi, err = _amdsmi()
-        if smi is None:
-            self.notes.append(err)
-            return
-        try:
-            smi.amdsmi_init()
-        except Exception as e:
-            self.notes.append(f"amdsmi_init failed: {e}")
-            return
-        self._smi = smi
-        try:
-            handles = smi.amdsmi_get_processor_handles()
-        except Exception as e:
-            self.notes.append(f"no GPU handles: {e}")
-            return
-        bus = _torch_bus_id(self.device_index)
-        chosen = None
-        if bus is not None:
-            for h in handles:
-                try:
-                    bdf = smi.amdsmi_get_gpu_device_bdf(h)  # "dddd:bb:dd.f"
-                    if int(bdf.split(":")[1], 16) == bus:
-                        chosen = h
-                        break
-                except Exception:
-                    continue
-        if chosen is None and len(handles) == 1:
-            chosen = handles[0]
-        if chosen is None:
-            self.notes.append(f"could not match torch device {self.device_index} "
-                              f"(bus {bus}) among {len(handles)} GPUs")
-            return
-        self._handle = chosen
+        self._smi, self._handle, notes = _open_handle(self.device_index)
+        self.notes.extend(notes)
 
     def _energy_j(self):
         if self._handle is None:

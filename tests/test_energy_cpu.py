@@ -53,3 +53,4 @@ def test_counter_that_did_not_advance_is_none():
     r = em.result()
     assert r["gpu_energy_j"] is None and r["gpu_mean_power_w"] is None
     assert any("did not advance" in n for n in r["notes"])
+
