@@ -374,25 +374,57 @@ def main():
         else:
             nbody.step(tp, tv, acc, tm, eps, 1.0, dt, 1, variant, plan=plan, diag=diag, pot=pot)
 
+    # Bring the GPU out of its idle clock state before the warm-up steps: force
+    # evaluations on the same inputs (no state change) for about 0.3 s.
+    t_ramp = time.perf_counter() + 0.3
+    while time.perf_counter() < t_ramp:
+        for _ in range(10):
+            if plan is not None:
+                plan.accel(tp, tm, 1.0, acc=acc, pot=pot)
+            elif hermite:
+                nbody.accel_jerk(tp, tv, tm, eps, 1.0, variant, acc=acc, jerk=jerk, pot=pot)
+            else:
+                nbody.accel(tp, tm, eps, 1.0, variant, acc=acc, pot=pot)
+        torch.cuda.synchronize()
+
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream(dev)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
+    # one event between consecutive steps: the first and last bracket the
+    # timed region, the others give per-step durations (median, min)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     nbody.timing_enable(plan is None)
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
-    start.record(stream)
-    for _ in range(args.steps):
+    marks[0].record(stream)
+    for s_ in range(args.steps):
         one_step()
-    stop.record(stream)
+        marks[s_ + 1].record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
-    ms_total = start.elapsed_time(stop)
+    ms_total = marks[0].elapsed_time(marks[-1])
+    step_ms = [marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps)]
     launches, kernel_ms = nbody.timing_read()
     nbody.timing_enable(False)
+
+    # The force evaluation alone (pack or staging, pair kernel, split
+    # combine, epilogue), repeated on the same inputs: median and minimum.
+    force_ms = []
+    for _ in range(max(args.steps, 5)):
+        a_ev = torch.cuda.Event(enable_timing=True)
+        b_ev = torch.cuda.Event(enable_timing=True)
+        a_ev.record(stream)
+        if plan is not None:
+            plan.accel(tp, tm, 1.0, acc=acc, pot=pot)
+        elif hermite:
+            nbody.accel_jerk(tp, tv, tm, eps, 1.0, variant, acc=acc, jerk=jerk, pot=pot)
+        else:
+            nbody.accel(tp, tm, eps, 1.0, variant, acc=acc, pot=pot)
+        b_ev.record(stream)
+        b_ev.synchronize()
+        force_ms.append(a_ev.elapsed_time(b_ev))
 
     if plan is not None:
         # The batched force kernel runs inside the graph replay: time it
@@ -427,6 +459,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step_median": round(float(np.median(step_ms)), 4),
+        "ms_per_step_min": round(float(np.min(step_ms)), 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -441,6 +475,13 @@ def main():
             "variant": variant,
             "n": n,
             "pairs_per_step": pairs_per_eval,
+        },
+        "force_evaluation": {
+            "what": "one " + ("acceleration + jerk" if hermite else "force") + " evaluation alone "
+                    "(pack, pair kernel, split combine, FP64 epilogue), repeated",
+            "ms_median": round(float(np.median(force_ms)), 4),
+            "ms_min": round(float(np.min(force_ms)), 4),
+            "G_pair_per_s_median": round(pairs_per_eval / (float(np.median(force_ms)) * 1e-3) / 1e9, 1),
         },
         "roofline": {
             "bound": "alu",
