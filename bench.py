@@ -179,27 +179,54 @@ def paper_run(variant, units=10.0, cpu_seconds=10.0):
     nbody.step_hermite(w, w.clone(), wa, wj, wm, eps, 1.0, dt, 1, variant)
     torch.cuda.synchronize()
 
+    def run_once(steps):
+        """One complete simulation; returns its wall time, the host
+        initial-conditions time, the final state and the diagnostics."""
+        t0 = time.perf_counter()
+        pos, vel, mass = ics.plummer(n, seed=spec["seed"])
+        t_ic = time.perf_counter() - t0
+        tp, tv, tm = (torch.from_numpy(x).to(dev) for x in (pos, vel, mass))
+        pot = torch.empty_like(tm)
+        acc, jerk, _ = nbody.accel_jerk(tp, tv, tm, eps, 1.0, variant, pot=pot)
+        d0 = nbody.step_hermite(tp, tv, acc, jerk, tm, eps, 1.0, 0.0, 1, variant, pot=pot)
+        diag = nbody.step_hermite(tp, tv, acc, jerk, tm, eps, 1.0, dt, steps, variant, pot=pot)
+        pf, vf = tp.cpu().numpy(), tv.cpu().numpy()
+        d = diag.cpu().numpy()
+        e0 = float(d0.cpu().numpy()[0, 2])
+        wall = time.perf_counter() - t0
+        return wall, t_ic, (pos, vel, mass, pf, vf), d, e0
+
     readings = (("ten steps", spec["steps"]), (f"{units:g} time units", int(round(units / dt))))
     for reading, steps in readings:
+        # A short run is repeated back to back (at least 3 times, about 3 s in
+        # all) so that the GPU energy counter, which advances at its own
+        # interval, spans it; time and energy are reported per run.
+        walls, ics_s = [], []
         with EnergyMeter() as em:
-            t0 = time.perf_counter()
-            pos, vel, mass = ics.plummer(n, seed=spec["seed"])
-            t_ic = time.perf_counter() - t0
-            tp, tv, tm = (torch.from_numpy(x).to(dev) for x in (pos, vel, mass))
-            pot = torch.empty_like(tm)
-            acc, jerk, _ = nbody.accel_jerk(tp, tv, tm, eps, 1.0, variant, pot=pot)
-            d0 = nbody.step_hermite(tp, tv, acc, jerk, tm, eps, 1.0, 0.0, 1, variant, pot=pot)
-            diag = nbody.step_hermite(tp, tv, acc, jerk, tm, eps, 1.0, dt, steps, variant, pot=pot)
-            pf, vf = tp.cpu().numpy(), tv.cpu().numpy()
-            d = diag.cpu().numpy()
-            e0 = float(d0.cpu().numpy()[0, 2])
-            wall = time.perf_counter() - t0
+            t_all = time.perf_counter()
+            while True:
+                wall, t_ic, state, d, e0 = run_once(steps)
+                walls.append(wall)
+                ics_s.append(t_ic)
+                if len(walls) >= 3 and time.perf_counter() - t_all >= 3.0:
+                    break
+                if steps > 100:
+                    break
         energy = em.result()
+        runs = len(walls)
+        energy["runs_measured"] = runs
+        for key in ("gpu_energy_j", "gpu_energy_from_power_samples_j", "host_energy_j"):
+            if energy.get(key) is not None:
+                energy[key.replace("_j", "_j_per_run")] = round(energy[key] / runs, 3)
+        pos, vel, mass, pf, vf = state
         de = np.abs(d[:, 2] - e0) / abs(e0)
+        wall = float(np.median(walls))
         out = {
             "paper_run": "plummer_102k", "reading": reading, "variant": variant, "n": n, "eps": eps,
             "dt": dt, "steps": steps, "force_jerk_evaluations": steps + 2,
-            "time_to_solution_s": round(wall, 3), "host_initial_conditions_s": round(t_ic, 3),
+            "time_to_solution_s": round(wall, 4), "runs": runs,
+            "time_to_solution_s_min": round(float(np.min(walls)), 4),
+            "host_initial_conditions_s": round(float(np.median(ics_s)), 4),
             "G_pair_per_s": round(float(n) * n * (steps + 2) / wall / 1e9, 1),
             "energy_drift_final": float(f"{de[-1]:.3e}"), "energy_drift_max": float(f"{de.max():.3e}"),
             "nonfinite": int(d[:, 13].max()),
@@ -209,6 +236,7 @@ def paper_run(variant, units=10.0, cpu_seconds=10.0):
         }
         if reading == "ten steps":
             # the final state's accelerations and jerks against the FP64 oracle
+            tp, tv, tm = (torch.from_numpy(x).to(dev) for x in (pf, vf, mass))
             ta, tj, _ = nbody.accel_jerk(tp, tv, tm, eps, 1.0, variant)
             tgt = orc.subsample_targets(n, 4096)
             ra, rj, _ = ocpu.accel_jerk(pf, vf, mass, eps, targets=tgt)
