@@ -305,7 +305,9 @@ struct JerkLayout {
   size_t packed, part, xp, vp, a1, j1, pot, diag, ctr, total;
 };
 
-JerkLayout jerk_layout(int64_t n, int32_t variant) {
+// `split` is the grid j-split the call will launch with (resolved once per
+// call, so a concurrent change of the tuning cannot outgrow the workspace).
+JerkLayout jerk_layout(int64_t n, int32_t variant, int split) {
   JerkLayout L{};
   const size_t un = static_cast<size_t>(n);
   const bool comp = variant == NBODY_FP32_COMP;
@@ -313,7 +315,6 @@ JerkLayout jerk_layout(int64_t n, int32_t variant) {
   L.packed = off;
   off += align_up(static_cast<size_t>(nb::padded(n)) * (comp ? 3 : 2) * sizeof(float4));
   L.part = off;
-  const int split = jerk_tune(variant, n).split;
   off += align_up(split > 1 ? static_cast<size_t>(split) * un * (comp ? 4 : 2) * sizeof(float4) : 0);
   L.xp = off;
   off += align_up(un * 3 * sizeof(double));
@@ -334,15 +335,14 @@ JerkLayout jerk_layout(int64_t n, int32_t variant) {
 }
 
 hipError_t enqueue_accel_jerk(const double *pos, const double *vel, const double *mass, int64_t n,
-                              double eps, double G, int32_t variant, double *acc, double *jerk,
-                              double *pot, void *ws, hipStream_t st) {
+                              double eps, double G, int32_t variant, const SingleTune &t,
+                              double *acc, double *jerk, double *pot, void *ws, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const JerkLayout L = jerk_layout(n, variant);
+  const JerkLayout L = jerk_layout(n, variant, t.split);
   const bool comp = variant == NBODY_FP32_COMP;
   float4 *packed = at<float4>(ws, L.packed);
   hipError_t e = nb::launch_pack_jerk(pos, vel, mass, n, comp, packed, st);
   if (e != hipSuccess) return e;
-  const SingleTune t = jerk_tune(variant, n);
   hipEvent_t stop = timing_begin(st);
   return nb::launch_pair_jerk(t.cfg, comp, packed, mass, n, eps, G, t.split, acc, jerk, pot,
                               at<float4>(ws, L.part), st, stop);
@@ -714,7 +714,7 @@ nbody_status nbody_step(double *pos, double *vel, double *acc, double *pot, cons
 
 size_t nbody_workspace_bytes_jerk(int64_t n, int32_t variant) {
   if (n < 0 || !valid_variant(variant)) return 0;
-  return jerk_layout(n, variant).total;
+  return jerk_layout(n, variant, jerk_tune(variant, n).split).total;
 }
 
 nbody_status nbody_accel_jerk(const double *pos, const double *vel, const double *mass, int64_t n,
@@ -739,11 +739,12 @@ nbody_status nbody_accel_jerk(const double *pos, const double *vel, const double
     for (int b = a + 1; b < 3; ++b)
       if (overlap(outs[a], outb[a], outs[b], outb[b])) return fail(NBODY_EINVAL, "outputs overlap each other");
   }
-  const size_t need = jerk_layout(n, variant).total;
+  const SingleTune t = jerk_tune(variant, n);
+  const size_t need = jerk_layout(n, variant, t.split).total;
   if (!ws) return fail(NBODY_EWORKSPACE, "workspace is NULL (need %zu bytes)", need);
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(NBODY_EWORKSPACE, "workspace must be 256-byte aligned");
   if (ws_bytes < need) return fail(NBODY_EWORKSPACE, "workspace of %zu bytes < %zu required", ws_bytes, need);
-  const hipError_t e = enqueue_accel_jerk(pos, vel, mass, n, eps, G, variant, acc, jerk, pot, ws,
+  const hipError_t e = enqueue_accel_jerk(pos, vel, mass, n, eps, G, variant, t, acc, jerk, pot, ws,
                                           static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "nbody_accel_jerk launch");
   return NBODY_OK;
@@ -774,7 +775,8 @@ nbody_status nbody_step_hermite(double *pos, double *vel, double *acc, double *j
     for (int a = 0; a < 6; ++a)
       if (overlap(diag, db, arr[a], ab[a])) return fail(NBODY_EINVAL, "diag overlaps the state arrays");
   }
-  const JerkLayout L = jerk_layout(n, variant);
+  const SingleTune t = jerk_tune(variant, n);
+  const JerkLayout L = jerk_layout(n, variant, t.split);
   if (!ws) return fail(NBODY_EWORKSPACE, "workspace is NULL (need %zu bytes)", L.total);
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(NBODY_EWORKSPACE, "workspace must be 256-byte aligned");
   if (ws_bytes < L.total) return fail(NBODY_EWORKSPACE, "workspace of %zu bytes < %zu required", ws_bytes, L.total);
@@ -786,7 +788,7 @@ nbody_status nbody_step_hermite(double *pos, double *vel, double *acc, double *j
   if (diag) e = nb::launch_fill_int(at<int>(ws, L.ctr), 1, 0, s);
   for (int32_t k = 0; k < n_steps && e == hipSuccess; ++k) {
     e = nb::launch_hermite_predict(pos, vel, acc, jerk, n, dt, xp, vp, s);
-    if (e == hipSuccess) e = enqueue_accel_jerk(xp, vp, mass, n, eps, G, variant, a1, j1, potw, ws, s);
+    if (e == hipSuccess) e = enqueue_accel_jerk(xp, vp, mass, n, eps, G, variant, t, a1, j1, potw, ws, s);
     if (e == hipSuccess) e = nb::launch_hermite_correct(pos, vel, acc, jerk, a1, j1, n, dt, s);
     if (e == hipSuccess && diag) {
       e = nb::launch_kick_diag(pos, vel, nullptr, potw, mass, n, 0.0, at<double>(ws, L.diag), s);

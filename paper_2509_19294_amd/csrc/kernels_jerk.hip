@@ -433,7 +433,8 @@ hipError_t launch_pair_jerk(int cfg, bool comp, const float4 *packed, const doub
                             double *pot, float4 *part, hipStream_t stream, hipEvent_t after_pair) {
   if (n <= 0) return hipSuccess;
   const int ib = jerk_targets_per_block(cfg);
-  if (ib == 0 || split > kMaxSplit) return hipErrorInvalidValue;
+  if (ib == 0 || split > kMaxSplit || (split > 1 && static_cast<int64_t>(split) * n > kPartCap))
+    return hipErrorInvalidValue;
   const int64_t nblk = (n + ib - 1) / ib;
   if (split < 1) split = 1;
   int64_t split_len = (n + split - 1) / split;
