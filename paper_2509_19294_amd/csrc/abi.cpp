@@ -110,8 +110,8 @@ int size_class(int64_t n) {
 // 10..20 for the plain and compensated forms; smaller classes take class 10's
 // entry and larger ones class 20's. Batched modes for classes 8..13.
 const SingleTune kTuned[2][11] = {
-    {{5, 4}, {5, 8}, {4, 4}, {4, 8}, {5, 16}, {4, 16}, {14, 32}, {14, 32}, {14, 32}, {14, 2}, {14, 2}},
-    {{5, 4}, {5, 8}, {5, 8}, {0, 16}, {15, 16}, {9, 32}, {9, 32}, {9, 32}, {9, 32}, {15, 2}, {9, 2}},
+    {{5, 4}, {5, 8}, {4, 4}, {4, 4}, {18, 16}, {18, 16}, {18, 32}, {14, 32}, {14, 32}, {18, 2}, {18, 2}},
+    {{5, 4}, {5, 8}, {5, 8}, {0, 16}, {18, 16}, {18, 16}, {9, 32}, {9, 32}, {9, 32}, {18, 2}, {9, 2}},
 };
 const int kTunedBatched[2][6] = {{8, 4, 4, 4, 4, 4}, {1, 4, 4, 4, 4, 4}};
 // Acceleration + jerk kernel: {shape, split} per size class 10..20, measured

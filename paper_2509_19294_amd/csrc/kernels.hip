@@ -407,23 +407,25 @@ __global__ __launch_bounds__(256) void pack_ds_kernel(const double *__restrict__
 // bounds checks. SW waves of a block share an i-group and take interleaved
 // groups of sources; their sums are combined through LDS in wave order.
 // One block (4 waves) computes targets [i0, i1) (packed index of i0 is ip0)
-// against packed sources [J0, J1); J1 - J0 must be a multiple of 4 * SW.
+// against packed sources [J0, J1); J1 - J0 must be a multiple of GS, the
+// number of sources a wave loads per group (4 or 8: one or two 64-byte
+// scalar loads in the plain form, two or four in the compensated form).
 // `X` is LDS scratch of smem_lds_floats<K, SW, COMP>() floats.
 template <int K, int SW, bool COMP>
 constexpr int smem_lds_floats() {
   return (SW > 1) ? (SW - 1) * (4 / SW) * 64 * K * 4 * (COMP ? 2 : 1) : 1;
 }
 
-template <int K, int SW, int TJ, bool COMP, bool EPS0>
+template <int K, int SW, int TJ, bool COMP, bool EPS0, int GS = 4>
 __device__ __forceinline__ void smem_block(const float4 *__restrict__ packed, int64_t i0,
                                            int64_t i1, int64_t ip0, int64_t J0, int64_t J1,
                                            float eps2f, float *X, const OutArgs &o) {
   constexpr int NW = 4;
   constexpr int NG = NW / SW;
   constexpr int JW = COMP ? 2 : 1;
-  constexpr int G = 4;                  // sources per group
+  constexpr int G = GS;                 // sources per group
   constexpr int STEP = SW * G;          // stride between a wave's groups
-  static_assert(NW % SW == 0 && TJ % G == 0, "bad shape");
+  static_assert(NW % SW == 0 && TJ % G == 0 && (G == 4 || G == 8), "bad shape");
 
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
@@ -474,15 +476,23 @@ __device__ __forceinline__ void smem_block(const float4 *__restrict__ packed, in
       const Quad *Qg = Qt + gi * (STEP * JW / 4);
       float4 H[G], L[G];
       if constexpr (COMP) {
-        const Quad c0 = Qg[0], c1 = Qg[1];
-        H[0] = c0.v[0]; L[0] = c0.v[1]; H[1] = c0.v[2]; L[1] = c0.v[3];
-        H[2] = c1.v[0]; L[2] = c1.v[1]; H[3] = c1.v[2]; L[3] = c1.v[3];
-      } else {
-        const Quad c0 = Qg[0];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-          H[g] = c0.v[g];
-          L[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int q = 0; q < G / 2; ++q) {
+          const Quad c = Qg[q];
+          H[2 * q] = c.v[0];
+          L[2 * q] = c.v[1];
+          H[2 * q + 1] = c.v[2];
+          L[2 * q + 1] = c.v[3];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < G / 4; ++q) {
+          const Quad c = Qg[q];
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            H[4 * q + g] = c.v[g];
+            L[4 * q + g] = make_float4(0.f, 0.f, 0.f, 0.f);
+          }
         }
       }
 #pragma unroll
@@ -587,7 +597,7 @@ __device__ __forceinline__ void smem_block(const float4 *__restrict__ packed, in
   }
 }
 
-template <int K, int SW, int TJ, bool COMP, bool EPS0>
+template <int K, int SW, int TJ, bool COMP, bool EPS0, int GS>
 __global__ __launch_bounds__(256) void pair_smem_kernel(const float4 *__restrict__ packed,
                                                         const double *__restrict__ mass,
                                                         int64_t n, float eps2f, int64_t split_len,
@@ -602,10 +612,12 @@ __global__ __launch_bounds__(256) void pair_smem_kernel(const float4 *__restrict
   const int64_t J1 = J0 + split_len < np ? J0 + split_len : np;
   OutArgs oo = o;
   oo.split_index = blockIdx.y;
-  smem_block<K, SW, TJ, COMP, EPS0>(packed, i0, i1, i0, J0, J1, eps2f, X, oo);
+  smem_block<K, SW, TJ, COMP, EPS0, GS>(packed, i0, i1, i0, J0, J1, eps2f, X, oo);
 }
 
-// Compiled single-system configurations: {block, k, ls, sw, tile, smem}.
+// Compiled single-system configurations: {block, k, ls, sw, tile, smem}
+// (smem: 0 = LDS tiles, 1 = scalar stream with 4-source groups, 2 = with
+// 8-source groups).
 static const PairCfg kSingle[] = {
     {256, 1, 1, 1, 256, 0},   // 0
     {256, 2, 1, 1, 256, 0},   // 1
@@ -623,6 +635,9 @@ static const PairCfg kSingle[] = {
     {256, 1, 1, 2, 256, 1},   // 13
     {256, 2, 1, 2, 256, 1},   // 14
     {256, 1, 1, 4, 256, 1},   // 15
+    {256, 1, 1, 1, 256, 2},   // 16
+    {256, 1, 1, 2, 256, 2},   // 17
+    {256, 1, 1, 4, 256, 2},   // 18
 };
 int single_cfg_count() { return static_cast<int>(sizeof(kSingle) / sizeof(kSingle[0])); }
 const PairCfg &single_cfg(int idx) { return kSingle[idx]; }
@@ -650,20 +665,20 @@ static hipError_t launch_single_t(bool comp, bool eps0, dim3 grid, const double 
   return hipGetLastError();
 }
 
-template <int K, int SW, int TJ>
+template <int K, int SW, int TJ, int GS>
 static hipError_t launch_smem_t(bool comp, bool eps0, dim3 grid, const double *mass,
                                 const float4 *packed, int64_t n, float eps2f, int64_t split_len,
                                 const OutArgs &o, hipStream_t st) {
   if (comp) {
     if (eps0)
-      pair_smem_kernel<K, SW, TJ, true, true><<<grid, 256, 0, st>>>(packed, mass, n, eps2f, split_len, o);
+      pair_smem_kernel<K, SW, TJ, true, true, GS><<<grid, 256, 0, st>>>(packed, mass, n, eps2f, split_len, o);
     else
-      pair_smem_kernel<K, SW, TJ, true, false><<<grid, 256, 0, st>>>(packed, mass, n, eps2f, split_len, o);
+      pair_smem_kernel<K, SW, TJ, true, false, GS><<<grid, 256, 0, st>>>(packed, mass, n, eps2f, split_len, o);
   } else {
     if (eps0)
-      pair_smem_kernel<K, SW, TJ, false, true><<<grid, 256, 0, st>>>(packed, mass, n, eps2f, split_len, o);
+      pair_smem_kernel<K, SW, TJ, false, true, GS><<<grid, 256, 0, st>>>(packed, mass, n, eps2f, split_len, o);
     else
-      pair_smem_kernel<K, SW, TJ, false, false><<<grid, 256, 0, st>>>(packed, mass, n, eps2f, split_len, o);
+      pair_smem_kernel<K, SW, TJ, false, false, GS><<<grid, 256, 0, st>>>(packed, mass, n, eps2f, split_len, o);
   }
   return hipGetLastError();
 }
@@ -712,8 +727,8 @@ hipError_t launch_pair_single(int cfg, bool comp, const double *pos, const doubl
   switch (cfg) {
 #define NB_CASE(I, B, K, LS, SW, T) \
   case I: e = launch_single_t<B, K, LS, SW, T>(comp, eps0, grid, pos, mass, packed, n, eps2f, split, split_len, o, stream); break;
-#define NB_SMEM(I, K, SW, T) \
-  case I: e = launch_smem_t<K, SW, T>(comp, eps0, grid, mass, packed, n, eps2f, split_len, o, stream); break;
+#define NB_SMEM(I, K, SW, T, GS) \
+  case I: e = launch_smem_t<K, SW, T, GS>(comp, eps0, grid, mass, packed, n, eps2f, split_len, o, stream); break;
     NB_CASE(0, 256, 1, 1, 1, 256)
     NB_CASE(1, 256, 2, 1, 1, 256)
     NB_CASE(2, 256, 4, 1, 1, 256)
@@ -724,12 +739,15 @@ hipError_t launch_pair_single(int cfg, bool comp, const double *pos, const doubl
     NB_CASE(7, 256, 2, 1, 4, 1024)
     NB_CASE(8, 256, 8, 1, 1, 256)
     NB_CASE(9, 256, 2, 2, 1, 512)
-    NB_SMEM(10, 1, 1, 256)
-    NB_SMEM(11, 2, 1, 256)
-    NB_SMEM(12, 4, 1, 256)
-    NB_SMEM(13, 1, 2, 256)
-    NB_SMEM(14, 2, 2, 256)
-    NB_SMEM(15, 1, 4, 256)
+    NB_SMEM(10, 1, 1, 256, 4)
+    NB_SMEM(11, 2, 1, 256, 4)
+    NB_SMEM(12, 4, 1, 256, 4)
+    NB_SMEM(13, 1, 2, 256, 4)
+    NB_SMEM(14, 2, 2, 256, 4)
+    NB_SMEM(15, 1, 4, 256, 4)
+    NB_SMEM(16, 1, 1, 256, 8)
+    NB_SMEM(17, 1, 2, 256, 8)
+    NB_SMEM(18, 1, 4, 256, 8)
 #undef NB_CASE
 #undef NB_SMEM
     default:
@@ -749,7 +767,9 @@ hipError_t launch_pair_single(int cfg, bool comp, const double *pos, const doubl
 // Batched: a persistent grid claims (cluster, i-block) work items, heaviest
 // first, from a global counter.
 
-// Modes: LDS-tiled (0-3) and scalar-stream (4-8) block shapes. Each mode's
+// Modes: LDS-tiled (0-3) and scalar-stream (4-8) block shapes. (Scalar-stream
+// modes with 8-source groups were measured and lost to mode 4 at every
+// cluster size class: items are too short to amortise the longer groups.) Each mode's
 // kernel gets the LDS its shape needs: the double-buffered tile for the LDS
 // modes (which also holds their cross-wave combine), the cross-wave combine
 // buffer for the scalar-stream ones.
@@ -757,6 +777,7 @@ constexpr int kBatchedTile[] = {512, 512, 512, 256, 0, 0, 0, 0, 0};
 constexpr int kBatchedK[] = {1, 1, 2, 2, 1, 1, 2, 1, 2};
 constexpr int kBatchedSW[] = {4, 2, 2, 1, 4, 2, 2, 1, 1};
 constexpr int kBatchedSmem[] = {0, 0, 0, 0, 1, 1, 1, 1, 1};
+static_assert(sizeof(kBatchedK) / sizeof(kBatchedK[0]) == kBatchedModes, "mode tables");
 
 template <int MODE, bool COMP>
 constexpr int batched_lds_float4() {
