@@ -46,7 +46,7 @@ DEFAULT_VARIANT = {"plummer_1k": "plain", "plummer_64k": "plain", "plummer_256k"
 # dispatch they were taken on: (workload, variant, cfg, split) -> bytes. A run
 # whose dispatch differs reports null.
 MEASURED_TRAFFIC = {
-    ("plummer_64k", "plain", 14, 32): 49328128,
+    ("plummer_64k", "plain", 18, 32): 49309696,
     # acceleration + jerk kernel (bench.py --hermite): shape 2, split 32
     ("plummer_64k", "plain", "jerk", 2, 32): 99073280,
 }
