@@ -215,7 +215,8 @@ nbody_status nbody_step_hermite(double *pos, double *vel, double *acc, double *j
 /* Shapes of the acceleration + jerk kernel, for the autotuner.
  * nbody_tune_jerk_count: number of compiled shapes. nbody_tune_jerk_describe
  * writes {K targets per lane, SW waves splitting the sources, targets per
- * block} to out3 (host memory). nbody_tune_jerk_set forces cfg + 1000 * split
+ * block} to out3 (host memory); shapes 8 and 9 repeat shapes 2 and 1 with
+ * eight sources per scalar-load group in the plain form. nbody_tune_jerk_set forces cfg + 1000 * split
  * (split 0 = the built-in rule) for every size of a variant; -1 returns to
  * the built-in table. nbody_tune_jerk_get returns cfg + 1000 * split as used
  * for n particles (-1 for invalid arguments). A forced split larger than the

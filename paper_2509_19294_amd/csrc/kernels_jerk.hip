@@ -68,13 +68,16 @@ struct JerkOut {
   double G;
 };
 
-template <int K, int SW, bool COMP, bool EPS0>
+// GS: sources a wave loads per group (4, or 8 for the plain form, whose
+// eight sources fit the scalar registers: 64 SGPRs).
+template <int K, int SW, bool COMP, bool EPS0, int GS>
 __global__ __launch_bounds__(256) void pair_jerk_kernel(const float4 *__restrict__ packed,
                                                         int64_t n, float eps2f, int64_t split_len,
                                                         JerkOut o) {
   constexpr int NW = 4, NG = NW / SW, IB = NG * 64 * K;
   constexpr int JW = jw_of<COMP>();
-  constexpr int G4 = 4;             // sources per group
+  constexpr int G4 = GS;            // sources per group
+  static_assert(GS == 4 || (GS == 8 && !COMP), "group size");
   constexpr int STEP = SW * G4;     // stride between a wave's groups
   constexpr int TJ = 256;           // sources per wave per tile
   // accumulated quantities: a (3), phi, J1 = sum s w (3), J2 = sum s beta d (3)
@@ -138,7 +141,7 @@ __global__ __launch_bounds__(256) void pair_jerk_kernel(const float4 *__restrict
       const Quad *Qg = Qt + gi * (STEP * JW / 4);
       float4 W[G4 * JW];
 #pragma unroll
-      for (int w = 0; w < JW; ++w) {
+      for (int w = 0; w < G4 * JW / 4; ++w) {
         const Quad qd = Qg[w];
 #pragma unroll
         for (int c = 0; c < 4; ++c) W[w * 4 + c] = qd.v[c];
@@ -351,25 +354,28 @@ __global__ __launch_bounds__(256) void hermite_correct_kernel(
   }
 }
 
-template <int K, int SW>
+// GS = 8 applies to the plain form; the compensated form keeps GS = 4.
+template <int K, int SW, int GS = 4>
 hipError_t launch_jerk_t(bool comp, bool eps0, dim3 grid, const float4 *packed, int64_t n,
                          float eps2f, int64_t split_len, const JerkOut &o, hipStream_t st) {
   if (comp) {
-    if (eps0) pair_jerk_kernel<K, SW, true, true><<<grid, 256, 0, st>>>(packed, n, eps2f, split_len, o);
-    else pair_jerk_kernel<K, SW, true, false><<<grid, 256, 0, st>>>(packed, n, eps2f, split_len, o);
+    if (eps0) pair_jerk_kernel<K, SW, true, true, 4><<<grid, 256, 0, st>>>(packed, n, eps2f, split_len, o);
+    else pair_jerk_kernel<K, SW, true, false, 4><<<grid, 256, 0, st>>>(packed, n, eps2f, split_len, o);
   } else {
-    if (eps0) pair_jerk_kernel<K, SW, false, true><<<grid, 256, 0, st>>>(packed, n, eps2f, split_len, o);
-    else pair_jerk_kernel<K, SW, false, false><<<grid, 256, 0, st>>>(packed, n, eps2f, split_len, o);
+    if (eps0) pair_jerk_kernel<K, SW, false, true, GS><<<grid, 256, 0, st>>>(packed, n, eps2f, split_len, o);
+    else pair_jerk_kernel<K, SW, false, false, GS><<<grid, 256, 0, st>>>(packed, n, eps2f, split_len, o);
   }
   return hipGetLastError();
 }
 
 // Compiled shapes: K targets per lane, SW of the block's four waves splitting
-// the sources of one target group.
+// the sources of one target group; shapes 8 and 9 load eight sources per
+// group in the plain form (four in the compensated form).
 struct JerkShape {
   int k, sw;
 };
-constexpr JerkShape kJerkShapes[] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2}, {2, 4}, {4, 1}, {4, 2}};
+constexpr JerkShape kJerkShapes[] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2},
+                                     {2, 4}, {4, 1}, {4, 2}, {1, 4}, {1, 2}};
 constexpr int kJerkShapeCount = static_cast<int>(sizeof(kJerkShapes) / sizeof(kJerkShapes[0]));
 
 hipError_t launch_jerk_shape(int cfg, bool comp, bool eps0, dim3 grid, const float4 *packed, int64_t n,
@@ -383,6 +389,8 @@ hipError_t launch_jerk_shape(int cfg, bool comp, bool eps0, dim3 grid, const flo
     case 5: return launch_jerk_t<2, 4>(comp, eps0, grid, packed, n, eps2f, split_len, o, st);
     case 6: return launch_jerk_t<4, 1>(comp, eps0, grid, packed, n, eps2f, split_len, o, st);
     case 7: return launch_jerk_t<4, 2>(comp, eps0, grid, packed, n, eps2f, split_len, o, st);
+    case 8: return launch_jerk_t<1, 4, 8>(comp, eps0, grid, packed, n, eps2f, split_len, o, st);
+    case 9: return launch_jerk_t<1, 2, 8>(comp, eps0, grid, packed, n, eps2f, split_len, o, st);
     default: return hipErrorInvalidValue;
   }
 }
