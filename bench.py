@@ -479,8 +479,8 @@ def main():
 
     out = {
         "metric": ("G pair-interactions/s (acceleration + jerk) and % FP32 VALU peak at rel-RMS "
-                   "accel err <=1e-5 vs FP64" if hermite else
-                   "G pair-interactions/s and % FP32 VALU peak at rel-RMS accel err <=1e-5 vs FP64"),
+                   "accel err \u22641e-5 vs FP64" if hermite else
+                   "G pair-interactions/s and % FP32 VALU peak at rel-RMS accel err \u22641e-5 vs FP64"),
         "value": round(value, 2),
         "unit": "G pair-interactions/s",
         "n_gpus": 1,

@@ -2,7 +2,7 @@
 
     python -m paper_2509_19294_amd.build
 
-compiles ``csrc/kernels.hip``, ``csrc/kernels_jerk.hip`` and ``csrc/abi.cpp`` into
+compiles ``csrc/kernels*.hip`` and ``csrc/abi.cpp`` into
 ``paper_2509_19294_amd/libnbody.so``. Packed FP32 instructions are disabled
 for device code (``-packed-fp32-ops``); the FP32 pair loop therefore issues
 one FP32 operation per lane per instruction.
@@ -41,6 +41,7 @@ def hipcc() -> str:
 
 def sources():
     return [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "kernels_jerk.hip"),
+            os.path.join(CSRC, "kernels_order.hip"), os.path.join(CSRC, "kernels_nf.hip"),
             os.path.join(CSRC, "abi.cpp")]
 
 

@@ -40,7 +40,7 @@ size_t align_up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 // Workspace layout (offsets in bytes from the base, each 256-byte aligned).
 struct WsLayout {
-  size_t packed, part, pot, diag, ctr, total;
+  size_t packed, part, pot, diag, ctr, order, total;
 };
 
 // Packed sources: padded(n) entries for a single system; a batched plan's
@@ -67,6 +67,9 @@ WsLayout ws_layout(int64_t n, int32_t variant, int32_t n_clusters = 1) {
   off += align_up(static_cast<size_t>(nb::kDiagBlocks) * nb::kDiagLen * sizeof(double));
   L.ctr = off;
   off += 256;
+  // spatial-order buffers of the near/far compensated kernel (single system)
+  L.order = off;
+  if (variant == NBODY_FP32_COMP && n_clusters <= 1 && n > 0) off += align_up(nb::order_ws_at(nullptr, n).bytes);
   L.total = off;
   return L;
 }
@@ -111,7 +114,7 @@ int size_class(int64_t n) {
 // entry and larger ones class 20's. Batched modes for classes 8..13.
 const SingleTune kTuned[2][11] = {
     {{5, 4}, {5, 8}, {4, 4}, {4, 4}, {18, 16}, {18, 16}, {18, 32}, {14, 32}, {14, 32}, {18, 2}, {18, 2}},
-    {{5, 4}, {5, 8}, {5, 8}, {0, 16}, {18, 16}, {18, 16}, {9, 32}, {9, 32}, {9, 32}, {18, 2}, {9, 2}},
+    {{5, 4}, {5, 8}, {5, 8}, {0, 16}, {18, 16}, {18, 16}, {9, 32}, {9, 32}, {19, 32}, {19, 2}, {19, 2}},
 };
 const int kTunedBatched[2][6] = {{8, 4, 4, 4, 4, 4}, {1, 4, 4, 4, 4, 4}};
 // Acceleration + jerk kernel: {shape, split} per size class 10..20, measured
@@ -154,7 +157,7 @@ nbody_status tune_load_locked(const char *path) {
       return fail(NBODY_EINVAL, "tuning file '%s' line %d malformed", path, lineno);
     }
     if (std::strcmp(kind, "single") == 0) {
-      if (a < 0 || a >= nb::single_cfg_count() || b < 1 || b > nb::kMaxSplit) {
+      if (a < 0 || a >= nb::single_cfg_count(v == NBODY_FP32_COMP) || b < 1 || b > nb::kMaxSplit) {
         std::fclose(f);
         return fail(NBODY_EINVAL, "tuning file '%s' line %d: bad single entry", path, lineno);
       }
@@ -290,6 +293,15 @@ hipError_t enqueue_accel(const double *pos, const double *mass, int64_t n, doubl
   const SingleTune t = single_tune(variant, n);
   const bool comp = variant == NBODY_FP32_COMP;
   float4 *packed = at<float4>(ws, L.packed);
+  if (nb::single_cfg(t.cfg).smem == 3) {
+    // near/far kernel on the spatial order (compensated form only)
+    const nb::OrderWs w = nb::order_ws_at(at<char>(ws, L.order), n);
+    const hipError_t e = nb::launch_order(pos, mass, n, w, st);
+    if (e != hipSuccess) return e;
+    hipEvent_t stop = timing_begin(st);
+    return nb::launch_pair_nf(nb::single_cfg(t.cfg).k, w, n, eps, G, t.split, acc, pot,
+                              at<float4>(ws, L.part), st, stop);
+  }
   const bool smem = nb::single_cfg(t.cfg).smem != 0;
   if (!comp || smem) {
     const hipError_t e = nb::launch_pack(pos, mass, n, packed, st, comp);
@@ -800,7 +812,7 @@ nbody_status nbody_step_hermite(double *pos, double *vel, double *acc, double *j
 }
 
 int32_t nbody_tune_count(int32_t variant) {
-  return valid_variant(variant) ? nb::single_cfg_count() : 0;
+  return valid_variant(variant) ? nb::single_cfg_count(variant == NBODY_FP32_COMP) : 0;
 }
 
 nbody_status nbody_tune_describe(int32_t variant, int32_t cfg, int32_t *out6) {
@@ -815,7 +827,8 @@ nbody_status nbody_tune_describe(int32_t variant, int32_t cfg, int32_t *out6) {
     std::memcpy(out6, v, sizeof(v));
     return NBODY_OK;
   }
-  if (cfg < 0 || cfg >= nb::single_cfg_count()) return fail(NBODY_EINVAL, "no configuration %d", cfg);
+  if (cfg < 0 || cfg >= nb::single_cfg_count(variant == NBODY_FP32_COMP))
+    return fail(NBODY_EINVAL, "no configuration %d", cfg);
   const nb::PairCfg &c = nb::single_cfg(cfg);
   const int32_t v[6] = {c.block, c.k, c.ls, c.sw, c.tile, nb::cfg_iblock(c)};
   std::memcpy(out6, v, sizeof(v));
@@ -829,7 +842,7 @@ nbody_status nbody_tune_set(int32_t variant, int32_t size_class_, int32_t cfg) {
   if (size_class_ < 0 || size_class_ >= kClasses) return fail(NBODY_EINVAL, "size class out of range");
   if (cfg != -1) {
     const int c = cfg % 1000, sp = cfg / 1000;
-    if (c < 0 || c >= nb::single_cfg_count() || sp < 0 || sp > nb::kMaxSplit)
+    if (c < 0 || c >= nb::single_cfg_count(variant == NBODY_FP32_COMP) || sp < 0 || sp > nb::kMaxSplit)
       return fail(NBODY_EINVAL, "bad configuration %d", cfg);
   }
   std::lock_guard<std::mutex> g(g_tune_mu);

@@ -638,8 +638,11 @@ static const PairCfg kSingle[] = {
     {256, 1, 1, 1, 256, 2},   // 16
     {256, 1, 1, 2, 256, 2},   // 17
     {256, 1, 1, 4, 256, 2},   // 18
+    {256, 2, 1, 1, 256, 3},   // 19: near/far on the spatial order, 512 i per block
+    {256, 4, 1, 1, 256, 3},   // 20: near/far, 1024 i per block
 };
 int single_cfg_count() { return static_cast<int>(sizeof(kSingle) / sizeof(kSingle[0])); }
+int single_cfg_count(bool comp) { return comp ? single_cfg_count() : 19; }
 const PairCfg &single_cfg(int idx) { return kSingle[idx]; }
 
 template <int BLOCK, int K, int LS, int SW, int TILE>
@@ -702,6 +705,7 @@ hipError_t launch_pair_single(int cfg, bool comp, const double *pos, const doubl
   if (n <= 0) return hipSuccess;
   if (cfg < 0 || cfg >= single_cfg_count()) return hipErrorInvalidValue;
   const PairCfg &c = kSingle[cfg];
+  if (c.smem == 3) return hipErrorInvalidValue;  // near/far: launch_order + launch_pair_nf
   const int64_t ib = cfg_iblock(c);
   const int64_t nblk = (n + ib - 1) / ib;
   if (split < 1) split = 1;

@@ -1,0 +1,316 @@
+// Near/far compensated pair kernel (gfx950).
+//
+// Works on the spatially ordered copy of the system (kernels_order.hip). A
+// block takes K * 256 consecutive ordered targets (K groups of 256, whose
+// bounding boxes give the block's box B, diagonal D) and uses the centre of
+// B as its FP64 frame c. Source tiles of 256 ordered particles are staged in
+// LDS relative to c, and each tile takes one of two paths, the same for the
+// whole block:
+//   * near (the tile's box lies closer to B than D / 2): double-single
+//     staging, separation (hi_j - hi_i) + (lo_j - lo_i), as in the
+//     compensated form;
+//   * far (box distance >= D / 2): hi parts only, separation hi_j - hi_i.
+// Far-path error: with |x_i - c| <= D / 2 and |x_j - c| <= |d| + D / 2,
+// rounding the two offsets to FP32 and subtracting moves d by at most
+// u (|x_i - c| + |x_j - c| + |d|) <= u (2 |d| + D) <= 4 u |d|, since every
+// pair of a far tile has |d| >= D / 2 (u = 2^-24): a few units of FP32
+// rounding of the separation itself, independent of where the system sits,
+// at the plain form's 13 operations per pair. The self pair falls in a near
+// tile (its box overlaps B) unless D = 0, where both offsets are exactly 0.
+// Tile sums are merged into (hi, lo) accumulators with TwoSum, as in the
+// compensated form; the order of every sum is fixed.
+#include "device_common.h"
+
+namespace nb {
+
+namespace {
+
+constexpr int kNfTile = kOrderGroup;  // sources per tile = particles per box group
+
+struct NfOut {
+  double *acc, *pot;      // direct results, indexed through perm (split == 1)
+  float4 *part;           // [split][n][2] partials in ordered index (split > 1)
+  const int32_t *perm;    // ordered index -> caller's index
+  int64_t n;
+  double G;
+};
+
+template <int K, bool EPS0>
+__global__ __launch_bounds__(256) void pair_nf_kernel(const double *__restrict__ spos,
+                                                      const double *__restrict__ smass,
+                                                      const double *__restrict__ box, int64_t n,
+                                                      float eps2f, int64_t split_len, NfOut o) {
+  constexpr int IB = 256 * K;
+  __shared__ float4 lds[2][2 * kNfTile];
+  const int tid = threadIdx.x;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * IB;
+  const int64_t i1 = i0 + IB < n ? i0 + IB : n;
+  const int64_t J0 = static_cast<int64_t>(blockIdx.y) * split_len;
+  const int64_t J1 = J0 + split_len < n ? J0 + split_len : n;
+
+  // the block's box: union of its groups' boxes; the frame is its centre
+  double bl[3], bh[3];
+  {
+    const int64_t g0 = i0 / kOrderGroup, g1 = (i1 - 1) / kOrderGroup;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      bl[c] = box[6 * g0 + c];
+      bh[c] = box[6 * g0 + 3 + c];
+    }
+    for (int64_t g = g0 + 1; g <= g1; ++g) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        bl[c] = fmin(bl[c], box[6 * g + c]);
+        bh[c] = fmax(bh[c], box[6 * g + 3 + c]);
+      }
+    }
+  }
+  const double cx = 0.5 * (bl[0] + bh[0]), cy = 0.5 * (bl[1] + bh[1]), cz = 0.5 * (bl[2] + bh[2]);
+  // far threshold: (D / 2)^2
+  const double D2 = 0.25 * ((bh[0] - bl[0]) * (bh[0] - bl[0]) + (bh[1] - bl[1]) * (bh[1] - bl[1]) +
+                            (bh[2] - bl[2]) * (bh[2] - bl[2]));
+
+  float xh[K], yh[K], zh[K], xl[K], yl[K], zl[K], mi[K];
+  int64_t iidx[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t i = i0 + static_cast<int64_t>(k) * 256 + tid;
+    iidx[k] = i;
+    const int64_t ic = i < i1 ? i : i1 - 1;
+    ds_split(spos[3 * ic] - cx, xh[k], xl[k]);
+    ds_split(spos[3 * ic + 1] - cy, yh[k], yl[k]);
+    ds_split(spos[3 * ic + 2] - cz, zh[k], zl[k]);
+    mi[k] = static_cast<float>(smass[ic]);
+  }
+
+  float ah[K][4], al[K][4];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ah[k][c] = al[k][c] = 0.f;
+
+  // tile t covers ordered sources [J0 + t * kNfTile, ...): box group
+  // (J0 / kNfTile) + t, since split boundaries are multiples of kNfTile
+  auto is_far = [&](int64_t t) {
+    const int64_t g = J0 / kNfTile + t;
+    double d2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double lo = box[6 * g + c], hi = box[6 * g + 3 + c];
+      const double gap = lo > bh[c] ? lo - bh[c] : (bl[c] > hi ? bl[c] - hi : 0.0);
+      d2 += gap * gap;
+    }
+    return d2 >= D2;
+  };
+
+  const int64_t ntiles = J1 > J0 ? (J1 - J0 + kNfTile - 1) / kNfTile : 0;
+  double sx = cx, sy = cy, sz = cz, sm = 0.0;  // staged source (registers)
+  auto load = [&](int64_t t) {
+    const int64_t j = J0 + t * kNfTile + tid;
+    if (j < J1) {
+      sx = spos[3 * j];
+      sy = spos[3 * j + 1];
+      sz = spos[3 * j + 2];
+      sm = smass[j];
+    } else {
+      sx = cx;
+      sy = cy;
+      sz = cz;
+      sm = 0.0;
+    }
+  };
+  auto store = [&](int buf, bool far) {
+    if (far) {
+      lds[buf][2 * tid] = make_float4(static_cast<float>(sx - cx), static_cast<float>(sy - cy),
+                                      static_cast<float>(sz - cz), static_cast<float>(sm));
+    } else {
+      float hx, hy, hz, lx, ly, lz;
+      ds_split(sx - cx, hx, lx);
+      ds_split(sy - cy, hy, ly);
+      ds_split(sz - cz, hz, lz);
+      lds[buf][2 * tid] = make_float4(hx, hy, hz, static_cast<float>(sm));
+      lds[buf][2 * tid + 1] = make_float4(lx, ly, lz, 0.f);
+    }
+  };
+
+  bool far_cur = false;
+  if (ntiles > 0) {
+    far_cur = is_far(0);
+    load(0);
+    store(0, far_cur);
+  }
+  __syncthreads();
+
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const int buf = static_cast<int>(t & 1);
+    const bool more = t + 1 < ntiles;
+    bool far_next = false;
+    if (more) {
+      far_next = is_far(t + 1);
+      load(t + 1);
+    }
+    const float4 *T = lds[buf];
+    float p[K][4];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) p[k][c] = 0.f;
+
+    if (far_cur) {
+#pragma unroll 8
+      for (int jj = 0; jj < kNfTile; ++jj) {
+        const float4 H = T[2 * jj];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float dx = H.x - xh[k], dy = H.y - yh[k], dz = H.z - zh[k];
+          float r2 = fmaf(dx, dx, eps2f);
+          r2 = fmaf(dy, dy, r2);
+          r2 = fmaf(dz, dz, r2);
+          float rho = rsq(r2);
+          if constexpr (EPS0) rho = r2 > 0.f ? rho : 0.f;
+          const float mr = H.w * rho;
+          const float s = mr * (rho * rho);
+          p[k][0] = fmaf(s, dx, p[k][0]);
+          p[k][1] = fmaf(s, dy, p[k][1]);
+          p[k][2] = fmaf(s, dz, p[k][2]);
+          p[k][3] += mr;
+        }
+      }
+    } else {
+#pragma unroll 8
+      for (int jj = 0; jj < kNfTile; ++jj) {
+        const float4 H = T[2 * jj], L = T[2 * jj + 1];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float dx = (H.x - xh[k]) + (L.x - xl[k]);
+          const float dy = (H.y - yh[k]) + (L.y - yl[k]);
+          const float dz = (H.z - zh[k]) + (L.z - zl[k]);
+          float r2 = fmaf(dx, dx, eps2f);
+          r2 = fmaf(dy, dy, r2);
+          r2 = fmaf(dz, dz, r2);
+          float rho = rsq(r2);
+          if constexpr (EPS0) rho = r2 > 0.f ? rho : 0.f;
+          const float mr = H.w * rho;
+          const float s = mr * (rho * rho);
+          p[k][0] = fmaf(s, dx, p[k][0]);
+          p[k][1] = fmaf(s, dy, p[k][1]);
+          p[k][2] = fmaf(s, dz, p[k][2]);
+          p[k][3] += mr;
+        }
+      }
+    }
+
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        float s, e;
+        two_sum(ah[k][c], p[k][c], s, e);
+        ah[k][c] = s;
+        al[k][c] += e;
+      }
+
+    if (more) store(buf ^ 1, far_next);
+    far_cur = far_next;
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t i = iidx[k];
+    if (i >= i1) continue;
+    if (o.part) {
+      float4 *P = o.part + (static_cast<int64_t>(blockIdx.y) * o.n + i) * 2;
+      P[0] = make_float4(ah[k][0], ah[k][1], ah[k][2], ah[k][3]);
+      P[1] = make_float4(al[k][0], al[k][1], al[k][2], al[k][3]);
+    } else {
+      double s[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) s[c] = static_cast<double>(ah[k][c]) + static_cast<double>(al[k][c]);
+      const int64_t d = o.perm[i];
+      o.acc[3 * d] = o.G * s[0];
+      o.acc[3 * d + 1] = o.G * s[1];
+      o.acc[3 * d + 2] = o.G * s[2];
+      if (o.pot) {
+        const double self = EPS0 ? 0.0 : static_cast<double>(self_term(mi[k], eps2f));
+        o.pot[d] = -o.G * (s[3] - self);
+      }
+    }
+  }
+}
+
+// Sums the split partials of ordered particle k in split order (FP64),
+// applies G and the self-term correction, and writes to the caller's index.
+__global__ __launch_bounds__(256) void combine_nf_kernel(const float4 *__restrict__ part, int split,
+                                                         int64_t n, const double *__restrict__ smass,
+                                                         const int32_t *__restrict__ perm,
+                                                         float eps2f, int eps0, double G,
+                                                         double *__restrict__ acc,
+                                                         double *__restrict__ pot) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (k >= n) return;
+  double s[4] = {0, 0, 0, 0};
+  for (int q = 0; q < split; ++q) {
+    const float4 *P = part + (static_cast<int64_t>(q) * n + k) * 2;
+    const float4 h = P[0], l = P[1];
+    s[0] += static_cast<double>(h.x) + static_cast<double>(l.x);
+    s[1] += static_cast<double>(h.y) + static_cast<double>(l.y);
+    s[2] += static_cast<double>(h.z) + static_cast<double>(l.z);
+    s[3] += static_cast<double>(h.w) + static_cast<double>(l.w);
+  }
+  const int64_t d = perm[k];
+  acc[3 * d] = G * s[0];
+  acc[3 * d + 1] = G * s[1];
+  acc[3 * d + 2] = G * s[2];
+  if (pot) {
+    const double self = eps0 ? 0.0 : static_cast<double>(self_term(static_cast<float>(smass[k]), eps2f));
+    pot[d] = -G * (s[3] - self);
+  }
+}
+
+template <int K>
+hipError_t launch_nf_t(bool eps0, dim3 grid, const OrderWs &w, int64_t n, float eps2f,
+                       int64_t split_len, const NfOut &o, hipStream_t st) {
+  if (eps0)
+    pair_nf_kernel<K, true><<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, n, eps2f, split_len, o);
+  else
+    pair_nf_kernel<K, false><<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, n, eps2f, split_len, o);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_pair_nf(int k, const OrderWs &w, int64_t n, double eps, double G, int split,
+                          double *acc, double *pot, float4 *part, hipStream_t stream,
+                          hipEvent_t after_pair) {
+  if (n <= 0) return hipSuccess;
+  if (k != 2 && k != 4) return hipErrorInvalidValue;
+  if (split < 1) split = 1;
+  if (split > max_split(n)) split = max_split(n);
+  int64_t split_len = (n + split - 1) / split;
+  split_len = (split_len + kNfTile - 1) / kNfTile * kNfTile;
+  const int64_t ib = 256 * static_cast<int64_t>(k);
+  const int64_t nblk = (n + ib - 1) / ib;
+  const float eps2f = static_cast<float>(eps * eps);
+  const bool eps0 = eps == 0.0;
+  NfOut o{};
+  o.G = G;
+  o.n = n;
+  o.perm = w.perm;
+  if (split > 1) {
+    o.part = part;
+  } else {
+    o.acc = acc;
+    o.pot = pot;
+  }
+  dim3 grid(static_cast<unsigned>(nblk), static_cast<unsigned>(split));
+  hipError_t e = k == 2 ? launch_nf_t<2>(eps0, grid, w, n, eps2f, split_len, o, stream)
+                        : launch_nf_t<4>(eps0, grid, w, n, eps2f, split_len, o, stream);
+  if (e == hipSuccess && after_pair) e = hipEventRecord(after_pair, stream);
+  if (e != hipSuccess || split == 1) return e;
+  combine_nf_kernel<<<static_cast<unsigned>((n + 255) / 256), 256, 0, stream>>>(
+      part, split, n, w.smass, w.perm, eps2f, eps0 ? 1 : 0, G, acc, pot);
+  return hipGetLastError();
+}
+
+}  // namespace nb

@@ -22,7 +22,9 @@ struct PairCfg {
   int ls;     // lanes sharing one i (intra-wave j-split, combined by shuffles)
   int sw;     // waves sharing one i-group (inter-wave j-split, combined in LDS)
   int tile;   // j-particles per tile (LDS-staged, or per wave for the scalar stream)
-  int smem;   // 0: j-tiles staged in LDS; 1: j streamed by scalar loads into SGPRs
+  int smem;   // 0: j-tiles staged in LDS; 1 (2): j streamed by scalar loads into
+              // SGPRs in groups of 4 (8); 3: near/far kernel on the spatial order
+              // (compensated form only)
 };
 
 // Largest grid j-split the workspace holds for n particles.
@@ -37,8 +39,10 @@ __host__ __device__ inline int64_t padded(int64_t n) { return (n + kPad - 1) / k
 // i-particles one block covers for an item.
 inline int cfg_iblock(const PairCfg &c) { return (c.block / 64 / c.sw) * (64 / c.ls) * c.k; }
 
-// Table of compiled single-system configurations (same table for both forms).
+// Table of compiled single-system configurations. The near/far ones (smem 3)
+// come last and exist for the compensated form only.
 int single_cfg_count();
+int single_cfg_count(bool comp);
 const PairCfg &single_cfg(int idx);
 
 // Batched modes compiled into the persistent kernel.
@@ -99,6 +103,27 @@ hipError_t launch_pair_batched(const BatchedArgs &b, const double *pos, const do
                                float4 *packed, double G, int *counters, double *acc, double *pot,
                                hipStream_t stream);
 int batched_grid(bool comp, int mode);  // persistent grid (blocks) for the current device
+
+// Spatial order (kernels_order.hip) and the near/far compensated pair kernel
+// (kernels_nf.hip). order_ws_at lays out the ordering buffers in a workspace
+// region at `base` (nullptr: sizes only, in .bytes).
+constexpr int kOrderGroup = 256;  // particles per bounding-box group (= nf tile)
+struct OrderWs {
+  size_t bytes;
+  double *moments;          // [256][6] partial moments
+  uint32_t *key0, *key1;    // [n] Morton keys (ping-pong)
+  int32_t *perm, *idx1;     // [n] ordered index -> caller's index (ping-pong)
+  uint32_t *hist, *scan;    // digit histograms and their scan's block totals
+  double *spos, *smass;     // [n][3], [n] in the order
+  double *box;              // [ceil(n / kOrderGroup)][6] min xyz, max xyz
+};
+OrderWs order_ws_at(void *base, int64_t n);
+hipError_t launch_order(const double *pos, const double *mass, int64_t n, const OrderWs &w,
+                        hipStream_t stream);
+// k = 2 or 4 targets per thread; writes acc/pot at the caller's indices.
+hipError_t launch_pair_nf(int k, const OrderWs &w, int64_t n, double eps, double G, int split,
+                          double *acc, double *pot, float4 *part, hipStream_t stream,
+                          hipEvent_t after_pair = nullptr);
 
 // Acceleration + jerk (kernels_jerk.hip). Packed sources hold 2 (plain) or
 // 3 (compensated) float4 per particle, padded(n) particles; partials hold
