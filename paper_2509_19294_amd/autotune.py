@@ -42,7 +42,8 @@ def _time(fn, reps, warm=1):
     return float(np.median(ts))
 
 
-def tune_single(variant, log2n, reps=5, splits=(1, 2, 4, 8, 16, 32), configs=None, log=None):
+def tune_single(variant, log2n, reps=5, splits=(1, 2, 4, 8, 16, 32), configs=None, log=None,
+                large_splits=(1, 2)):
     import torch
 
     n = 1 << log2n
@@ -58,7 +59,7 @@ def tune_single(variant, log2n, reps=5, splits=(1, 2, 4, 8, 16, 32), configs=Non
     # large systems: fewer repetitions and no deep splits
     if n >= (1 << 19):
         reps = min(reps, 2)
-        splits = tuple(s for s in splits if s <= 2)
+        splits = tuple(s for s in splits if s in large_splits)
     try:
         for c in idx:
             for sp in splits:
@@ -168,7 +169,13 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-jerk", action="store_true")
+    ap.add_argument("--configs", default=None,
+                    help="comma-separated single-system configurations to time (default: all)")
+    ap.add_argument("--large-splits", default="1,2",
+                    help="grid splits timed for systems of 2^19 particles and more")
     args = ap.parse_args()
+    cfg_list = [int(c) for c in args.configs.split(",")] if args.configs else None
+    large = tuple(int(c) for c in args.large_splits.split(","))
     nbody.load()
     nbody.tune_reset()
     lines = ["# kind variant class cfg [split] -- written by paper_2509_19294_amd.autotune"]
@@ -181,7 +188,7 @@ def main():
     for variant in args.variants.split(","):
         v = nbody.VARIANTS[variant]
         for c in ([] if args.no_single else range(args.min_log2, args.max_log2 + 1)):
-            (cfg, sp, ms), _ = tune_single(variant, c, log=log)
+            (cfg, sp, ms), _ = tune_single(variant, c, log=log, configs=cfg_list, large_splits=large)
             lines.append(f"single {v} {c} {cfg} {sp}")
             print(f"# best {variant} 2^{c}: cfg {cfg} split {sp} {ms:.4f} ms", flush=True)
         for c in ([] if args.no_jerk else range(args.min_log2, args.max_log2 + 1)):

@@ -113,8 +113,8 @@ int size_class(int64_t n) {
 // 10..20 for the plain and compensated forms; smaller classes take class 10's
 // entry and larger ones class 20's. Batched modes for classes 8..13.
 const SingleTune kTuned[2][11] = {
-    {{5, 4}, {5, 8}, {4, 4}, {4, 4}, {18, 16}, {18, 16}, {18, 32}, {14, 32}, {14, 32}, {18, 2}, {18, 2}},
-    {{5, 4}, {5, 8}, {5, 8}, {0, 16}, {18, 16}, {18, 16}, {9, 32}, {9, 32}, {19, 32}, {19, 2}, {19, 2}},
+    {{5, 4}, {5, 8}, {4, 4}, {4, 4}, {18, 16}, {18, 16}, {18, 32}, {14, 32}, {14, 32}, {14, 8}, {14, 8}},
+    {{5, 4}, {5, 8}, {5, 8}, {0, 16}, {18, 16}, {18, 16}, {9, 32}, {23, 32}, {23, 32}, {23, 8}, {23, 8}},
 };
 const int kTunedBatched[2][6] = {{8, 4, 4, 4, 4, 4}, {1, 4, 4, 4, 4, 4}};
 // Acceleration + jerk kernel: {shape, split} per size class 10..20, measured
@@ -299,8 +299,8 @@ hipError_t enqueue_accel(const double *pos, const double *mass, int64_t n, doubl
     const hipError_t e = nb::launch_order(pos, mass, n, w, st);
     if (e != hipSuccess) return e;
     hipEvent_t stop = timing_begin(st);
-    return nb::launch_pair_nf(nb::single_cfg(t.cfg).k, w, n, eps, G, t.split, acc, pot,
-                              at<float4>(ws, L.part), st, stop);
+    return nb::launch_pair_nf(nb::single_cfg(t.cfg).k, nb::single_cfg(t.cfg).sw, w, n, eps, G, t.split,
+                              acc, pot, at<float4>(ws, L.part), st, stop);
   }
   const bool smem = nb::single_cfg(t.cfg).smem != 0;
   if (!comp || smem) {

@@ -640,6 +640,9 @@ static const PairCfg kSingle[] = {
     {256, 1, 1, 4, 256, 2},   // 18
     {256, 2, 1, 1, 256, 3},   // 19: near/far on the spatial order, 512 i per block
     {256, 4, 1, 1, 256, 3},   // 20: near/far, 1024 i per block
+    {256, 4, 1, 4, 256, 3},   // 21: near/far, 256 i, four waves split the sources
+    {256, 4, 1, 2, 256, 3},   // 22: near/far, 512 i, two waves per target group
+    {256, 2, 1, 2, 256, 3},   // 23: near/far, 256 i, two waves per target group
 };
 int single_cfg_count() { return static_cast<int>(sizeof(kSingle) / sizeof(kSingle[0])); }
 int single_cfg_count(bool comp) { return comp ? single_cfg_count() : 19; }

@@ -1,9 +1,11 @@
 // Near/far compensated pair kernel (gfx950).
 //
 // Works on the spatially ordered copy of the system (kernels_order.hip). A
-// block takes K * 256 consecutive ordered targets (K groups of 256, whose
-// bounding boxes give the block's box B, diagonal D) and uses the centre of
-// B as its FP64 frame c. Source tiles of 256 ordered particles are staged in
+// block (four waves) takes IB = (4 / SW) * 64 * K consecutive ordered targets
+// (K per lane; SW waves share a target group and split each tile's sources,
+// their sums combined through LDS in wave order); the bounding boxes of the
+// IB / 256 groups give the block's box B, diagonal D, and the centre of B is
+// its FP64 frame c. Source tiles of 256 ordered particles are staged in
 // LDS relative to c, and each tile takes one of two paths, the same for the
 // whole block:
 //   * near (the tile's box lies closer to B than D / 2): double-single
@@ -35,14 +37,27 @@ struct NfOut {
   double G;
 };
 
-template <int K, bool EPS0>
+template <int K, int SW>
+constexpr int nf_lds_float4() {
+  constexpr int tiles = 2 * 2 * kNfTile;
+  constexpr int combine = SW > 1 ? ((SW - 1) * (4 / SW) * 64 * K * 8 + 3) / 4 : 1;
+  return tiles > combine ? tiles : combine;
+}
+
+template <int K, int SW, bool EPS0>
 __global__ __launch_bounds__(256) void pair_nf_kernel(const double *__restrict__ spos,
                                                       const double *__restrict__ smass,
                                                       const double *__restrict__ box, int64_t n,
                                                       float eps2f, int64_t split_len, NfOut o) {
-  constexpr int IB = 256 * K;
-  __shared__ float4 lds[2][2 * kNfTile];
+  constexpr int NG = 4 / SW;          // target groups of 64 lanes per block
+  constexpr int IB = NG * 64 * K;
+  static_assert(IB % kOrderGroup == 0 && 4 % SW == 0, "block shape");
+  __shared__ float4 smem[nf_lds_float4<K, SW>()];
+  float4 (*lds)[2 * kNfTile] = reinterpret_cast<float4 (*)[2 * kNfTile]>(smem);
   const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const int wj = wave % SW, wg = wave / SW;
   const int64_t i0 = static_cast<int64_t>(blockIdx.x) * IB;
   const int64_t i1 = i0 + IB < n ? i0 + IB : n;
   const int64_t J0 = static_cast<int64_t>(blockIdx.y) * split_len;
@@ -74,7 +89,7 @@ __global__ __launch_bounds__(256) void pair_nf_kernel(const double *__restrict__
   int64_t iidx[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int64_t i = i0 + static_cast<int64_t>(k) * 256 + tid;
+    const int64_t i = i0 + static_cast<int64_t>(k) * (NG * 64) + wg * 64 + lane;
     iidx[k] = i;
     const int64_t ic = i < i1 ? i : i1 - 1;
     ds_split(spos[3 * ic] - cx, xh[k], xl[k]);
@@ -158,7 +173,7 @@ __global__ __launch_bounds__(256) void pair_nf_kernel(const double *__restrict__
 
     if (far_cur) {
 #pragma unroll 8
-      for (int jj = 0; jj < kNfTile; ++jj) {
+      for (int jj = wj; jj < kNfTile; jj += SW) {
         const float4 H = T[2 * jj];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -178,7 +193,7 @@ __global__ __launch_bounds__(256) void pair_nf_kernel(const double *__restrict__
       }
     } else {
 #pragma unroll 8
-      for (int jj = 0; jj < kNfTile; ++jj) {
+      for (int jj = wj; jj < kNfTile; jj += SW) {
         const float4 H = T[2 * jj], L = T[2 * jj + 1];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -214,6 +229,40 @@ __global__ __launch_bounds__(256) void pair_nf_kernel(const double *__restrict__
     far_cur = far_next;
     __syncthreads();
   }
+
+  // waves sharing a target group: waves 1..SW-1 park their sums in LDS (the
+  // tile buffers are free after the last barrier), wave 0 adds them in order
+  if constexpr (SW > 1) {
+    float *X = reinterpret_cast<float *>(smem);
+    constexpr int SLOT = NG * 64 * K * 8;
+    const int base = (wg * 64 + lane) * K * 8;
+    if (wj > 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          X[(wj - 1) * SLOT + base + k * 8 + 2 * c] = ah[k][c];
+          X[(wj - 1) * SLOT + base + k * 8 + 2 * c + 1] = al[k][c];
+        }
+    }
+    __syncthreads();
+    if (wj == 0) {
+      for (int w = 1; w < SW; ++w) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const float oh = X[(w - 1) * SLOT + base + k * 8 + 2 * c];
+            const float ol = X[(w - 1) * SLOT + base + k * 8 + 2 * c + 1];
+            float s, e;
+            two_sum(ah[k][c], oh, s, e);
+            ah[k][c] = s;
+            al[k][c] = (al[k][c] + ol) + e;
+          }
+      }
+    }
+  }
+  if (wj != 0) return;
 
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -268,28 +317,27 @@ __global__ __launch_bounds__(256) void combine_nf_kernel(const float4 *__restric
   }
 }
 
-template <int K>
+template <int K, int SW>
 hipError_t launch_nf_t(bool eps0, dim3 grid, const OrderWs &w, int64_t n, float eps2f,
                        int64_t split_len, const NfOut &o, hipStream_t st) {
   if (eps0)
-    pair_nf_kernel<K, true><<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, n, eps2f, split_len, o);
+    pair_nf_kernel<K, SW, true><<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, n, eps2f, split_len, o);
   else
-    pair_nf_kernel<K, false><<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, n, eps2f, split_len, o);
+    pair_nf_kernel<K, SW, false><<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, n, eps2f, split_len, o);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_pair_nf(int k, const OrderWs &w, int64_t n, double eps, double G, int split,
-                          double *acc, double *pot, float4 *part, hipStream_t stream,
+hipError_t launch_pair_nf(int k, int sw, const OrderWs &w, int64_t n, double eps, double G,
+                          int split, double *acc, double *pot, float4 *part, hipStream_t stream,
                           hipEvent_t after_pair) {
   if (n <= 0) return hipSuccess;
-  if (k != 2 && k != 4) return hipErrorInvalidValue;
   if (split < 1) split = 1;
   if (split > max_split(n)) split = max_split(n);
   int64_t split_len = (n + split - 1) / split;
   split_len = (split_len + kNfTile - 1) / kNfTile * kNfTile;
-  const int64_t ib = 256 * static_cast<int64_t>(k);
+  const int64_t ib = (4 / sw) * 64 * static_cast<int64_t>(k);
   const int64_t nblk = (n + ib - 1) / ib;
   const float eps2f = static_cast<float>(eps * eps);
   const bool eps0 = eps == 0.0;
@@ -304,8 +352,13 @@ hipError_t launch_pair_nf(int k, const OrderWs &w, int64_t n, double eps, double
     o.pot = pot;
   }
   dim3 grid(static_cast<unsigned>(nblk), static_cast<unsigned>(split));
-  hipError_t e = k == 2 ? launch_nf_t<2>(eps0, grid, w, n, eps2f, split_len, o, stream)
-                        : launch_nf_t<4>(eps0, grid, w, n, eps2f, split_len, o, stream);
+  hipError_t e;
+  if (k == 2 && sw == 1) e = launch_nf_t<2, 1>(eps0, grid, w, n, eps2f, split_len, o, stream);
+  else if (k == 4 && sw == 1) e = launch_nf_t<4, 1>(eps0, grid, w, n, eps2f, split_len, o, stream);
+  else if (k == 4 && sw == 4) e = launch_nf_t<4, 4>(eps0, grid, w, n, eps2f, split_len, o, stream);
+  else if (k == 4 && sw == 2) e = launch_nf_t<4, 2>(eps0, grid, w, n, eps2f, split_len, o, stream);
+  else if (k == 2 && sw == 2) e = launch_nf_t<2, 2>(eps0, grid, w, n, eps2f, split_len, o, stream);
+  else return hipErrorInvalidValue;
   if (e == hipSuccess && after_pair) e = hipEventRecord(after_pair, stream);
   if (e != hipSuccess || split == 1) return e;
   combine_nf_kernel<<<static_cast<unsigned>((n + 255) / 256), 256, 0, stream>>>(

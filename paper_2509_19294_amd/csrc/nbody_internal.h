@@ -120,9 +120,10 @@ struct OrderWs {
 OrderWs order_ws_at(void *base, int64_t n);
 hipError_t launch_order(const double *pos, const double *mass, int64_t n, const OrderWs &w,
                         hipStream_t stream);
-// k = 2 or 4 targets per thread; writes acc/pot at the caller's indices.
-hipError_t launch_pair_nf(int k, const OrderWs &w, int64_t n, double eps, double G, int split,
-                          double *acc, double *pot, float4 *part, hipStream_t stream,
+// (k targets per lane, sw waves per target group) in {(2,1), (4,1), (4,4),
+// (4,2), (2,2)}; writes acc/pot at the caller's indices.
+hipError_t launch_pair_nf(int k, int sw, const OrderWs &w, int64_t n, double eps, double G,
+                          int split, double *acc, double *pot, float4 *part, hipStream_t stream,
                           hipEvent_t after_pair = nullptr);
 
 // Acceleration + jerk (kernels_jerk.hip). Packed sources hold 2 (plain) or

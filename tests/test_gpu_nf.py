@@ -1,4 +1,4 @@
-"""GPU parity of the near/far compensated kernel (configurations 19 and 20 of
+"""GPU parity of the near/far compensated kernel (configurations 19-23 of
 the compensated form): spatial ordering, per-block frames, hi-only far
 tiles. Same tolerances as the compensated form (rel-RMS <= 1e-5, worst
 particle <= 1e-4); results must be bitwise reproducible, translation must not
@@ -16,7 +16,7 @@ from paper_2509_19294_amd import ics, nbody
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-NF_CFGS = (19, 20)
+NF_CFGS = (19, 20, 21, 22, 23)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -51,7 +51,7 @@ def check(a, p, ra, rp, what):
 
 
 def test_configurations_exist_for_compensated_only():
-    assert len(nbody.tune_configs("comp")) == len(nbody.tune_configs("plain")) + 2
+    assert len(nbody.tune_configs("comp")) == len(nbody.tune_configs("plain")) + len(NF_CFGS)
     with pytest.raises(nbody.NbodyError):
         nbody.tune_set("plain", 10, 19, 1)
 
