@@ -57,7 +57,11 @@ typedef int32_t nbody_status;
 #define NBODY_FP32_PLAIN 0  /* FP32 coordinates and sums (two-level: per tile, then running) */
 #define NBODY_FP32_COMP 1   /* FP32 pair arithmetic on double-single (hi, lo) coordinates
                                relative to a per-block FP64 frame, compensated (TwoSum)
-                               accumulation, FP64 epilogue */
+                               accumulation, FP64 epilogue. For large systems the library
+                               orders the particles spatially (internally; results stay at
+                               the caller's indices) and source tiles far from a block
+                               drop the lo parts, which keeps every separation within
+                               4 ulps of its own size */
 
 /* One diagnostics row (float64), written after every step by nbody_step. */
 #define NBODY_DIAG_LEN 16
