@@ -290,9 +290,11 @@ hipError_t enqueue_accel(const double *pos, const double *mass, int64_t n, doubl
                          int32_t variant, double *acc, double *pot, void *ws, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const WsLayout L = ws_layout(n, variant);
-  const SingleTune t = single_tune(variant, n);
+  SingleTune t = single_tune(variant, n);
   const bool comp = variant == NBODY_FP32_COMP;
   float4 *packed = at<float4>(ws, L.packed);
+  // the spatial order indexes particles with 32-bit integers
+  if (nb::single_cfg(t.cfg).smem == 3 && n >= (int64_t{1} << 31)) t = SingleTune{9, t.split};
   if (nb::single_cfg(t.cfg).smem == 3) {
     // near/far kernel on the spatial order (compensated form only)
     const nb::OrderWs w = nb::order_ws_at(at<char>(ws, L.order), n);
