@@ -47,6 +47,8 @@ DEFAULT_VARIANT = {"plummer_1k": "plain", "plummer_64k": "plain", "plummer_256k"
 # whose dispatch differs reports null.
 MEASURED_TRAFFIC = {
     ("plummer_64k", "plain", 18, 32): 49309696,
+    # near/far compensated kernel, configuration 23
+    ("plummer_256k", "comp", 23, 32): 332125184,
     # acceleration + jerk kernel (bench.py --hermite): shape 2, split 32
     ("plummer_64k", "plain", "jerk", 2, 32): 99073280,
 }
