@@ -154,7 +154,7 @@ PAPER_ENERGY_TO_SOLUTION_KJ = {"wormhole_n300_plus_host": 71.56, "cpu_2x_epyc_91
 
 
 def paper_run(variant, units=10.0, cpu_seconds=10.0):
-    """The paper's representative run (Section 5) on one GPU: N = 102,400
+    """The paper's representative run (Section 4) on one GPU: N = 102,400
     Plummer sphere, fourth-order Hermite with acceleration + jerk on the GPU
     and the FP64 update on the GPU. The paper does not define its "time
     cycle"; two readings are run: ten steps, and ten N-body time units at the

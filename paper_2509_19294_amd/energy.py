@@ -3,7 +3,7 @@ own energy accumulator, GPU power sampled in a background thread, host CPU
 package energy from the Linux powercap (RAPL) files when they are readable.
 
 The paper integrates card power sampled at about 1 Hz and reads CPU package
-energy through RAPL over the simulation's wall-clock span (Section 5). Here
+energy through RAPL over the simulation's wall-clock span (Section 4). Here
 the GPU's cumulative energy counter gives the integral directly (no sampling
 error); the power samples (default 10 Hz) give the mean and the peak. Every
 source that is missing or not permitted is reported as None with a note,

@@ -186,7 +186,7 @@ WORKLOADS = {
     "plummer_256k": dict(n=262144, seed=4, eps=0.002, dt=1.0 / 512, steps=1000, masses="equal"),
     "ensemble_512": dict(k=512, seed=2, dt=1.0 / 256, steps=100),
     "kroupa_1m": dict(n=1048576, seed=3, eps=0.001, dt=1.0 / 1024, steps=10, masses="kroupa"),
-    # The paper's representative run (Section 5): 102,400 particles, ten steps.
+    # The paper's representative run (Section 4): 102,400 particles, ten steps.
     "plummer_102k": dict(n=102400, seed=5, eps=0.005, dt=1.0 / 256, steps=10, masses="equal"),
 }
 
