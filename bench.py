@@ -339,8 +339,8 @@ def copy_calibration(mib: int = 1024, reps: int = 5):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 "
-                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
+                          "(the library has no multi-GPU path)"}))
         sys.exit(2)
 
     if args.copy_calibration:

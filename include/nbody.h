@@ -49,7 +49,7 @@ extern "C" {
 typedef int32_t nbody_status;
 #define NBODY_OK 0
 #define NBODY_EINVAL 1      /* a null pointer, size or scalar out of range   */
-#define NBODY_ENOTSUP 2     /* a variant or size this build does not handle  */
+#define NBODY_ENOTSUP 2     /* a variant or size the library does not handle */
 #define NBODY_EWORKSPACE 3  /* workspace missing or smaller than required    */
 #define NBODY_EHIP 4        /* the HIP runtime returned an error             */
 

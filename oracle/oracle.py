@@ -29,7 +29,7 @@ What it computes, and where that comes from:
   x_p = x + v dt + a dt^2/2 + j dt^3/6, v_p = v + a dt + j dt^2/2; evaluate
   a_1, j_1 at (x_p, v_p); correct v_1 = v + (a_0 + a_1) dt/2 + (j_0 - j_1) dt^2/12,
   x_1 = x + (v + v_1) dt/2 + (a_0 - a_1) dt^2/12.
-* Error metrics used to judge the GPU results against this oracle.
+* Error metrics used to compare the GPU results with this oracle.
 
 Everything is float64. Sums over j use numpy reductions of whole rows (a
 different association order than a sequential loop, which is immaterial at
