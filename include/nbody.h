@@ -217,7 +217,9 @@ nbody_status nbody_step_hermite(double *pos, double *vel, double *acc, double *j
                                 size_t ws_bytes, void *stream);
 
 /* Shapes of the acceleration + jerk kernel, for the autotuner.
- * nbody_tune_jerk_count: number of compiled shapes. nbody_tune_jerk_describe
+ * nbody_tune_jerk_count: number of compiled shapes valid for a variant (0 for
+ * an unknown variant); shapes 10 and 11 (compensated form only) run the
+ * near/far kernel on the spatial order. nbody_tune_jerk_describe
  * writes {K targets per lane, SW waves splitting the sources, targets per
  * block} to out3 (host memory); shapes 8 and 9 repeat shapes 2 and 1 with
  * eight sources per scalar-load group in the plain form. nbody_tune_jerk_set forces cfg + 1000 * split
@@ -227,7 +229,7 @@ nbody_status nbody_step_hermite(double *pos, double *vel, double *acc, double *j
  * one a workspace was sized for makes the next call fail with
  * NBODY_EWORKSPACE: size workspaces after forcing. nbody_tune_reset also
  * clears the forced jerk shape. */
-int32_t nbody_tune_jerk_count(void);
+int32_t nbody_tune_jerk_count(int32_t variant);
 nbody_status nbody_tune_jerk_describe(int32_t cfg, int32_t *out3);
 nbody_status nbody_tune_jerk_set(int32_t variant, int32_t cfg);
 int32_t nbody_tune_jerk_get(int32_t variant, int64_t n);

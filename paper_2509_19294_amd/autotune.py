@@ -80,7 +80,7 @@ def tune_single(variant, log2n, reps=5, splits=(1, 2, 4, 8, 16, 32), configs=Non
     return best, rows
 
 
-def tune_jerk(variant, log2n, reps=5, splits=(1, 2, 4, 8, 16, 32), log=None):
+def tune_jerk(variant, log2n, reps=5, splits=(1, 2, 4, 8, 16, 32), log=None, shape_list=None):
     """Time every acceleration + jerk kernel shape with every grid j-split on
     a Plummer sphere of 2^log2n particles; returns the fastest."""
     import torch
@@ -89,12 +89,14 @@ def tune_jerk(variant, log2n, reps=5, splits=(1, 2, 4, 8, 16, 32), log=None):
     pos, vel, mass = ics.plummer(n, seed=2000 + log2n)
     tp, tv, tm = (torch.from_numpy(x).cuda() for x in (pos, vel, mass))
     acc, jerk, pot = torch.empty_like(tp), torch.empty_like(tp), torch.empty_like(tm)
-    shapes = nbody.jerk_shapes()
+    shapes = nbody.jerk_shapes(variant)
     if n >= (1 << 19):
         reps = min(reps, 2)
     best, rows = None, []
     try:
         for c, (k, sw, ib) in enumerate(shapes):
+            if shape_list is not None and c not in shape_list:
+                continue
             for sp in splits:
                 if sp > 1 and (math.ceil(n / ib) * sp > 64 * 1024 or n // sp < 1024 or sp * n > (1 << 23)):
                     continue
@@ -170,7 +172,7 @@ def main():
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-jerk", action="store_true")
     ap.add_argument("--configs", default=None,
-                    help="comma-separated single-system configurations to time (default: all)")
+                    help="comma-separated configurations (or jerk shapes) to time (default: all)")
     ap.add_argument("--large-splits", default="1,2",
                     help="grid splits timed for systems of 2^19 particles and more")
     args = ap.parse_args()
@@ -192,7 +194,7 @@ def main():
             lines.append(f"single {v} {c} {cfg} {sp}")
             print(f"# best {variant} 2^{c}: cfg {cfg} split {sp} {ms:.4f} ms", flush=True)
         for c in ([] if args.no_jerk else range(args.min_log2, args.max_log2 + 1)):
-            (cfg, sp, ms), _ = tune_jerk(variant, c, log=log)
+            (cfg, sp, ms), _ = tune_jerk(variant, c, log=log, shape_list=cfg_list)
             lines.append(f"jerk {v} {c} {cfg} {sp}")
             print(f"# best jerk {variant} 2^{c}: shape {cfg} split {sp} {ms:.4f} ms", flush=True)
         if not args.no_batched:

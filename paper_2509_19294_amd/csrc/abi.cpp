@@ -122,7 +122,7 @@ const int kTunedBatched[2][6] = {{8, 4, 4, 4, 4, 4}, {1, 4, 4, 4, 4, 4}};
 // eps = 0.01; split 0 would select the rule of jerk_default_split).
 const SingleTune kTunedJerk[2][11] = {
     {{8, 1}, {8, 2}, {8, 4}, {2, 8}, {2, 16}, {2, 32}, {2, 32}, {2, 32}, {2, 16}, {2, 8}, {1, 8}},
-    {{2, 1}, {2, 2}, {2, 4}, {2, 8}, {2, 16}, {2, 16}, {2, 16}, {2, 32}, {1, 32}, {0, 16}, {2, 4}},
+    {{2, 1}, {2, 2}, {2, 4}, {2, 8}, {2, 16}, {10, 32}, {10, 32}, {11, 32}, {10, 32}, {10, 16}, {10, 8}},
 };
 SingleTune g_jerk[2][kClasses];
 int g_jerk_forced[2] = {-1, -1};
@@ -169,7 +169,7 @@ nbody_status tune_load_locked(const char *path) {
       }
       g_batched[v][c] = a;
     } else if (std::strcmp(kind, "jerk") == 0) {
-      if (a < 0 || a >= nb::jerk_shape_count() || b < 0 || b > nb::kMaxSplit) {
+      if (a < 0 || a >= nb::jerk_shape_count(v == NBODY_FP32_COMP) || b < 0 || b > nb::kMaxSplit) {
         std::fclose(f);
         return fail(NBODY_EINVAL, "tuning file '%s' line %d: bad jerk entry", path, lineno);
       }
@@ -316,7 +316,7 @@ hipError_t enqueue_accel(const double *pos, const double *mass, int64_t n, doubl
 
 // Workspace of the jerk / Hermite calls.
 struct JerkLayout {
-  size_t packed, part, xp, vp, a1, j1, pot, diag, ctr, total;
+  size_t packed, part, xp, vp, a1, j1, pot, diag, ctr, order, svel, total;
 };
 
 // `split` is the grid j-split the call will launch with (resolved once per
@@ -344,6 +344,14 @@ JerkLayout jerk_layout(int64_t n, int32_t variant, int split) {
   off += align_up(static_cast<size_t>(nb::kDiagBlocks) * nb::kDiagLen * sizeof(double));
   L.ctr = off;
   off += 256;
+  // spatial order and ordered velocities of the near/far kernel
+  L.order = off;
+  L.svel = off;
+  if (variant == NBODY_FP32_COMP && n > 0) {
+    off += align_up(nb::order_ws_at(nullptr, n).bytes);
+    L.svel = off;
+    off += align_up(un * 3 * sizeof(double));
+  }
   L.total = off;
   return L;
 }
@@ -354,11 +362,24 @@ hipError_t enqueue_accel_jerk(const double *pos, const double *vel, const double
   if (n <= 0) return hipSuccess;
   const JerkLayout L = jerk_layout(n, variant, t.split);
   const bool comp = variant == NBODY_FP32_COMP;
+  if (nb::jerk_shape_nf(t.cfg) && comp && n < (int64_t{1} << 31)) {
+    const nb::OrderWs w = nb::order_ws_at(at<char>(ws, L.order), n);
+    hipError_t e = nb::launch_order(pos, mass, n, w, st);
+    double *svel = at<double>(ws, L.svel);
+    if (e == hipSuccess) e = nb::launch_gather_vel(vel, w, n, svel, st);
+    if (e != hipSuccess) return e;
+    int k = 0, sw = 0;
+    nb::jerk_shape(t.cfg, &k, &sw);
+    hipEvent_t stop = timing_begin(st);
+    return nb::launch_pair_nf_jerk(k, sw, w, svel, n, eps, G, t.split, acc, jerk, pot,
+                                   at<float4>(ws, L.part), st, stop);
+  }
+  const int cfg = nb::jerk_shape_nf(t.cfg) ? 2 : t.cfg;  // beyond 2^31 particles
   float4 *packed = at<float4>(ws, L.packed);
   hipError_t e = nb::launch_pack_jerk(pos, vel, mass, n, comp, packed, st);
   if (e != hipSuccess) return e;
   hipEvent_t stop = timing_begin(st);
-  return nb::launch_pair_jerk(t.cfg, comp, packed, mass, n, eps, G, t.split, acc, jerk, pot,
+  return nb::launch_pair_jerk(cfg, comp, packed, mass, n, eps, G, t.split, acc, jerk, pot,
                               at<float4>(ws, L.part), st, stop);
 }
 
@@ -896,7 +917,9 @@ nbody_status nbody_timing_read(int64_t *launches, double *total_ms) {
   return NBODY_OK;
 }
 
-int32_t nbody_tune_jerk_count(void) { return nb::jerk_shape_count(); }
+int32_t nbody_tune_jerk_count(int32_t variant) {
+  return valid_variant(variant) ? nb::jerk_shape_count(variant == NBODY_FP32_COMP) : 0;
+}
 
 nbody_status nbody_tune_jerk_describe(int32_t cfg, int32_t *out3) {
   g_err.clear();
@@ -915,7 +938,7 @@ nbody_status nbody_tune_jerk_set(int32_t variant, int32_t cfg) {
   if (!valid_variant(variant)) return fail(NBODY_ENOTSUP, "unknown variant %d", variant);
   if (cfg != -1) {
     const int c = cfg % 1000, sp = cfg / 1000;
-    if (cfg < 0 || c >= nb::jerk_shape_count() || sp > nb::kMaxSplit)
+    if (cfg < 0 || c >= nb::jerk_shape_count(variant == NBODY_FP32_COMP) || sp > nb::kMaxSplit)
       return fail(NBODY_EINVAL, "bad jerk configuration %d", cfg);
   }
   std::lock_guard<std::mutex> g(g_tune_mu);

@@ -374,8 +374,10 @@ hipError_t launch_jerk_t(bool comp, bool eps0, dim3 grid, const float4 *packed, 
 struct JerkShape {
   int k, sw;
 };
-constexpr JerkShape kJerkShapes[] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2},
-                                     {2, 4}, {4, 1}, {4, 2}, {1, 4}, {1, 2}};
+constexpr JerkShape kJerkShapes[] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2}, {2, 4},
+                                     {4, 1}, {4, 2}, {1, 4}, {1, 2}, {1, 1}, {2, 2}};
+// shapes 10 and 11: near/far kernel on the spatial order (compensated form)
+constexpr int kJerkFirstNf = 10;
 constexpr int kJerkShapeCount = static_cast<int>(sizeof(kJerkShapes) / sizeof(kJerkShapes[0]));
 
 hipError_t launch_jerk_shape(int cfg, bool comp, bool eps0, dim3 grid, const float4 *packed, int64_t n,
@@ -391,6 +393,7 @@ hipError_t launch_jerk_shape(int cfg, bool comp, bool eps0, dim3 grid, const flo
     case 7: return launch_jerk_t<4, 2>(comp, eps0, grid, packed, n, eps2f, split_len, o, st);
     case 8: return launch_jerk_t<1, 4, 8>(comp, eps0, grid, packed, n, eps2f, split_len, o, st);
     case 9: return launch_jerk_t<1, 2, 8>(comp, eps0, grid, packed, n, eps2f, split_len, o, st);
+    // near/far shapes run through launch_pair_nf_jerk
     default: return hipErrorInvalidValue;
   }
 }
@@ -404,6 +407,8 @@ unsigned elementwise_grid(int64_t n3) {
 }  // namespace
 
 int jerk_shape_count() { return kJerkShapeCount; }
+int jerk_shape_count(bool comp) { return comp ? kJerkShapeCount : kJerkFirstNf; }
+bool jerk_shape_nf(int cfg) { return cfg >= kJerkFirstNf && cfg < kJerkShapeCount; }
 
 int jerk_targets_per_block(int cfg) {
   if (cfg < 0 || cfg >= kJerkShapeCount) return 0;

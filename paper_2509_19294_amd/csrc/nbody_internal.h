@@ -129,9 +129,19 @@ hipError_t launch_pair_nf(int k, int sw, const OrderWs &w, int64_t n, double eps
 // Acceleration + jerk (kernels_jerk.hip). Packed sources hold 2 (plain) or
 // 3 (compensated) float4 per particle, padded(n) particles; partials hold
 // split x n x (2 or 4) float4.
-// Compiled kernel shapes: cfg in [0, jerk_shape_count()); K targets per
-// lane and SW waves splitting the sources of a target group.
+// Compiled kernel shapes: cfg in [0, jerk_shape_count(comp)); K targets per
+// lane and SW waves splitting the sources of a target group. The near/far
+// shapes (jerk_shape_nf) exist for the compensated form only and run on the
+// spatial order (launch_order, launch_gather_vel, launch_pair_nf_jerk).
 int jerk_shape_count();
+int jerk_shape_count(bool comp);
+bool jerk_shape_nf(int cfg);
+hipError_t launch_gather_vel(const double *vel, const OrderWs &w, int64_t n, double *svel,
+                             hipStream_t stream);
+hipError_t launch_pair_nf_jerk(int k, int sw, const OrderWs &w, const double *svel, int64_t n,
+                               double eps, double G, int split, double *acc, double *jerk,
+                               double *pot, float4 *part, hipStream_t stream,
+                               hipEvent_t after_pair = nullptr);
 void jerk_shape(int cfg, int *k, int *sw);
 int jerk_targets_per_block(int cfg);
 int jerk_default_split(int64_t n, int cfg);

@@ -76,7 +76,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                        sz, c_dp]),
             "nbody_step_hermite": (i32, [c_dp, c_dp, c_dp, c_dp, c_dp, c_dp, i64, dbl, dbl, dbl, i32,
                                          i32, c_dp, c_dp, sz, c_dp]),
-            "nbody_tune_jerk_count": (i32, []),
+            "nbody_tune_jerk_count": (i32, [i32]),
             "nbody_tune_jerk_describe": (i32, [i32, ctypes.POINTER(i32)]),
             "nbody_tune_jerk_set": (i32, [i32, i32]),
             "nbody_tune_jerk_get": (i32, [i32, i64]),
@@ -375,13 +375,13 @@ def tune_get(variant, n: int):
     return code % 1000, max(code // 1000, 1)
 
 
-def jerk_shapes():
-    """List of (K, SW, targets per block) of the compiled acceleration + jerk
-    kernel shapes."""
+def jerk_shapes(variant="plain"):
+    """List of (K, SW, targets per block) of the acceleration + jerk kernel
+    shapes compiled for a variant."""
     lib = load()
     buf = (ctypes.c_int32 * 3)()
     out = []
-    for c in range(lib.nbody_tune_jerk_count()):
+    for c in range(lib.nbody_tune_jerk_count(_variant(variant))):
         _check(lib.nbody_tune_jerk_describe(c, buf))
         out.append(tuple(buf))
     return out

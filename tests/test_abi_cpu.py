@@ -224,11 +224,15 @@ def test_jerk_entry_points_validate(lib):
 
 def test_jerk_shapes_and_forcing(lib, tmp_path):
     shapes = nbody.jerk_shapes()
-    assert len(shapes) == lib.nbody_tune_jerk_count() >= 4
+    assert len(shapes) == lib.nbody_tune_jerk_count(0) >= 4
+    assert lib.nbody_tune_jerk_count(1) == len(shapes) + 2 and lib.nbody_tune_jerk_count(9) == 0
+    assert lib.nbody_tune_jerk_set(0, 10) == nbody.EINVAL   # near/far shapes: compensated only
+    assert lib.nbody_tune_jerk_set(1, 10) == nbody.OK
+    assert lib.nbody_tune_jerk_set(1, -1) == nbody.OK
     for k, sw, ib in shapes:
         assert k in (1, 2, 4) and sw in (1, 2, 4) and ib == (4 // sw) * 64 * k
     buf = (ctypes.c_int32 * 3)()
-    assert lib.nbody_tune_jerk_describe(len(shapes), buf) == nbody.EINVAL
+    assert lib.nbody_tune_jerk_describe(lib.nbody_tune_jerk_count(1), buf) == nbody.EINVAL
     assert lib.nbody_tune_jerk_describe(0, None) == nbody.EINVAL
     assert lib.nbody_tune_jerk_set(0, len(shapes)) == nbody.EINVAL
     assert lib.nbody_tune_jerk_set(0, 33 * 1000) == nbody.EINVAL

@@ -107,7 +107,7 @@ def test_every_shape_and_split(variant, eps):
     pos, vel, mass = ics.plummer(n, seed=77)
     refs = references(pos, vel, mass, eps, variant)
     try:
-        for cfg in range(len(nbody.jerk_shapes())):
+        for cfg in range(len(nbody.jerk_shapes(variant))):
             for split in (1, 3, 4):
                 nbody.tune_jerk_set(variant, cfg, split)
                 assert nbody.tune_jerk_get(variant, n) == (cfg, split)
@@ -117,6 +117,54 @@ def test_every_shape_and_split(variant, eps):
                 assert all(np.array_equal(x, y) for x, y in zip(got, again)), (cfg, split)
     finally:
         nbody.tune_jerk_set(variant, -1)
+
+
+@pytest.mark.parametrize("cfg", [10, 11])
+def test_near_far_shapes(cfg):
+    """Near/far shapes (compensated form): tiny and ragged sizes, eps 0,
+    a translated and boosted system, a permuted input, bitwise
+    reproducibility and the full oracle at N = 65,536."""
+    try:
+        for n, eps in ((1, 0.01), (2, 0.0), (257, 0.01), (3001, 0.0), (3001, 0.01)):
+            pos, vel, mass = ics.plummer(n, seed=500 + n)
+            nbody.tune_jerk_set("comp", cfg, 2)
+            got = gpu_accel_jerk(pos, vel, mass, eps, "comp")
+            if n == 1:
+                assert all(np.all(x == 0) for x in got)
+                continue
+            check(got, references(pos, vel, mass, eps, "comp"), (cfg, n, eps))
+            again = gpu_accel_jerk(pos, vel, mass, eps, "comp")
+            assert all(np.array_equal(x, y) for x, y in zip(got, again))
+        pos, vel, mass = ics.plummer(4000, seed=61)
+        refs = references(pos, vel, mass, 0.01, "comp")
+        got = gpu_accel_jerk(pos + np.array([1e4, -2e3, 5e2]), vel + np.array([30.0, 0.0, -7.0]), mass, 0.01, "comp")
+        check(got, refs, (cfg, "boosted"))
+        perm = np.random.default_rng(3).permutation(4000)
+        got = gpu_accel_jerk(pos[perm], vel[perm], mass[perm], 0.01, "comp")
+        check(got, tuple(tuple(x[perm] for x in r) for r in refs), (cfg, "permuted"))
+        pos, vel, mass, spec = ics.workload("plummer_64k")
+        nbody.tune_jerk_set("comp", cfg, 16)
+        got = gpu_accel_jerk(pos, vel, mass, spec["eps"], "comp")
+        e = check(got, references(pos, vel, mass, spec["eps"], "comp", ocpu.accel_jerk), (cfg, "64k"))
+        print(f"near/far jerk shape {cfg} N=65536: acc {e[0]:.3e} jerk {e[1]:.3e} paper {e[2]:.3e}")
+    finally:
+        nbody.tune_jerk_set("comp", -1)
+
+
+def test_hermite_with_near_far_shape():
+    pos, vel, mass, spec = ics.workload("plummer_1k")
+    eps, dt, steps = spec["eps"], spec["dt"], spec["steps"]
+    pr, vr, _, _, _, rows = orc.hermite(pos, vel, mass, eps, 1.0, dt, steps)
+    nbody.tune_jerk_set("comp", 11, 2)
+    try:
+        tp, tv, tm = T(pos), T(vel), T(mass)
+        acc, jerk, _ = nbody.accel_jerk(tp, tv, tm, eps, 1.0, "comp")
+        diag = nbody.step_hermite(tp, tv, acc, jerk, tm, eps, 1.0, dt, steps, "comp")
+        torch.cuda.synchronize()
+    finally:
+        nbody.tune_jerk_set("comp", -1)
+    assert np.abs(tp.cpu().numpy() - pr).max() < 1e-7
+    np.testing.assert_allclose(diag.cpu().numpy()[:, 2], rows[1:, 2], rtol=1e-5)
 
 
 def test_jerk_boosted_and_shifted_frame():
