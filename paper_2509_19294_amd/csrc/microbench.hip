@@ -19,10 +19,18 @@
 //     a DPP row rotation (free on VOP2 instructions) and add the source-side
 //     contribution back through the inverse rotation; one evaluation serves
 //     two interactions
+//  13 the pair arithmetic with the accumulation moved to the matrix cores:
+//     per chain and iteration 3 sub, 3 fma, rsq and 2 mul on the VALU, then
+//     two v_mfma_f32_4x4x1_16b_f32 (sixteen 4x4 outer products: the
+//     sources' mass-weighted coordinates times r^-3, and masses times r^-1)
+//     in place of the 3 fma + 1 add into the accumulators; sources differ
+//     per lane, as that lane layout needs
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
@@ -76,6 +84,7 @@ __global__ __launch_bounds__(1024) void mb_kernel(float *out, int iters, float s
   __shared__ float4 tile[256];
   const float tf = 1e-7f * static_cast<float>(threadIdx.x);
   float a[ILP], y[ILP], ax[ILP], ay[ILP], az[ILP], ap[ILP];
+  f4 mD[ILP], mP[ILP];
   double d[ILP];
 #pragma unroll
   for (int k = 0; k < ILP; ++k) {
@@ -83,6 +92,8 @@ __global__ __launch_bounds__(1024) void mb_kernel(float *out, int iters, float s
     y[k] = 1.5f + 0.01f * k + tf;
     d[k] = static_cast<double>(a[k]);
     ax[k] = ay[k] = az[k] = ap[k] = 0.f;
+    mD[k] = f4{0.f, 0.f, 0.f, 0.f};
+    mP[k] = f4{0.f, 0.f, 0.f, 0.f};
   }
   // Runtime values, so the compiler cannot fold them into literals.
   const float b = 0.9999999f + tf * 1e-3f, c = 1e-7f + tf * 1e-9f;
@@ -91,6 +102,7 @@ __global__ __launch_bounds__(1024) void mb_kernel(float *out, int iters, float s
     __syncthreads();
   }
   float sx = 0.1f + tf, sy = 0.2f, sz = -0.3f, sm = 1e-3f, e2 = 1e-4f;
+  float bq = 0.7f + tf;  // per-lane matrix operand (OP 13)
   float d2[4] = {0.f, 0.f, 0.f, 0.f};
   for (int it = 0; it < iters; ++it) {
 #pragma unroll
@@ -131,6 +143,15 @@ __global__ __launch_bounds__(1024) void mb_kernel(float *out, int iters, float s
         ay[k] = fmaf(s, dy, ay[k]);
         az[k] = fmaf(s, dz, az[k]);
         ap[k] += mr;
+      } else if constexpr (OP == 13) {
+        const float dx = sx - a[k], dy = sy - y[k], dz = sz - a[k];
+        float r2 = fmaf(dx, dx, e2);
+        r2 = fmaf(dy, dy, r2);
+        r2 = fmaf(dz, dz, r2);
+        const float rho = rsq(r2);
+        const float r3 = rho * (rho * rho);
+        mD[k] = __builtin_amdgcn_mfma_f32_4x4x1f32(r3, bq, mD[k], 0, 0, 0);
+        mP[k] = __builtin_amdgcn_mfma_f32_4x4x1f32(rho, sm, mP[k], 0, 0, 0);
       } else if constexpr (OP == 12) {
         // handled below, once per iteration
       } else if constexpr (OP == 11) {
@@ -145,6 +166,12 @@ __global__ __launch_bounds__(1024) void mb_kernel(float *out, int iters, float s
       // a new source every iteration (wave-uniform, as an LDS broadcast is)
       sx = sx * 0.999f + 1e-3f;
       sy = sy * 0.999f - 1e-3f;
+    }
+    if constexpr (OP == 13) {
+      // a new source every iteration (per lane)
+      sx = sx * 0.999f + 1e-3f;
+      sy = sy * 0.999f - 1e-3f;
+      bq = bq * 0.999f + 1e-4f;
     }
     if constexpr (OP == 12) {
       float tz[ILP], tm[ILP];
@@ -178,7 +205,8 @@ __global__ __launch_bounds__(1024) void mb_kernel(float *out, int iters, float s
   float s = 0.f;
 #pragma unroll
   for (int k = 0; k < ILP; ++k)
-    s += a[k] + y[k] + static_cast<float>(d[k]) + ax[k] + ay[k] + az[k] + ap[k];
+    s += a[k] + y[k] + static_cast<float>(d[k]) + ax[k] + ay[k] + az[k] + ap[k] + mD[k][0] +
+         mD[k][1] + mD[k][2] + mD[k][3] + mP[k][0] + mP[k][1] + mP[k][2] + mP[k][3];
   s += d2[0] + d2[1] + d2[2] + d2[3];
   out[static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x] = s;
 }
@@ -204,7 +232,8 @@ hipError_t launch_op(int op, float *out, int blocks, int threads, int iters) {
     case 9: return launch<9, ILP>(out, blocks, threads, iters);
     case 10: return launch<10, ILP>(out, blocks, threads, iters);
     case 11: return launch<11, ILP>(out, blocks, threads, iters);
-    default: return launch<12, ILP>(out, blocks, threads, iters);
+    case 12: return launch<12, ILP>(out, blocks, threads, iters);
+    default: return launch<13, ILP>(out, blocks, threads, iters);
   }
 }
 
@@ -219,7 +248,7 @@ extern "C" {
 // Returns 0 on success, -1 on bad arguments, else the HIP error code.
 int mb_run(int op, int ilp, float *out, int blocks, int threads, int iters, int reps,
            double *ms_out) {
-  if (op < 0 || op > 12 || reps < 1 || reps > 64 || !out || !ms_out || blocks < 1 ||
+  if (op < 0 || op > 13 || reps < 1 || reps > 64 || !out || !ms_out || blocks < 1 ||
       threads < 64 || threads > 1024 || threads % 64 != 0 || iters < 1)
     return -1;
   if (ilp != 1 && ilp != 2 && ilp != 4 && ilp != 8 && ilp != 16) return -1;

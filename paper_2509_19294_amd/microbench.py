@@ -37,6 +37,7 @@ OPS = {
     10: ("pair_arith", 14),
     11: ("lds_bcast+4fma_f32", 5),
     12: ("sym_rot_pair_arith", 16 * 19),   # per chain-iteration: 16 pair evaluations
+    13: ("pair_arith_mfma_accum", 11),     # 8 VALU + rsq + 2 MFMA per interaction
 }
 
 # (op, ilp, blocks, threads)
@@ -51,6 +52,7 @@ CASES = [
     (10, 2, 512, 256), (10, 4, 512, 256), (10, 4, 256, 256), (10, 8, 256, 256),
     (11, 8, 4096, 256),
     (12, 2, 4096, 256), (12, 4, 4096, 256), (12, 8, 4096, 256), (12, 4, 1024, 256),
+    (13, 1, 4096, 256), (13, 2, 4096, 256), (13, 4, 4096, 256), (13, 8, 4096, 256),
 ]
 
 
@@ -90,7 +92,7 @@ def run(reps: int = 5, clock_ghz: float = 2.4, target: float = 3e10):
         row = {"op": name, "ilp": ilp, "blocks": blocks, "threads": threads,
                "waves_per_simd": round(waves_per_simd, 2), "ms": round(ms.value, 4),
                "lane_instr_per_cu_clk": round(rate / (cus * clock_ghz * 1e9), 2)}
-        if op in (10, 12):
+        if op in (10, 12, 13):
             # each symmetric evaluation serves two interactions
             per_eval = 2 if op == 12 else 1
             evals = 16 if op == 12 else 1
