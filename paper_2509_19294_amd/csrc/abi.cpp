@@ -121,7 +121,7 @@ const int kTunedBatched[2][6] = {{8, 4, 4, 4, 4, 4}, {1, 4, 4, 4, 4, 4}};
 // on MI355X by the same autotuner (Plummer spheres of 2^c particles,
 // eps = 0.01; split 0 would select the rule of jerk_default_split).
 const SingleTune kTunedJerk[2][11] = {
-    {{8, 1}, {8, 2}, {8, 4}, {2, 8}, {2, 16}, {2, 32}, {2, 32}, {2, 32}, {2, 16}, {2, 8}, {1, 8}},
+    {{8, 1}, {8, 2}, {8, 4}, {2, 8}, {2, 16}, {2, 16}, {2, 32}, {0, 32}, {0, 32}, {0, 16}, {0, 8}},
     {{2, 1}, {2, 2}, {2, 4}, {2, 8}, {2, 16}, {10, 32}, {10, 32}, {11, 32}, {10, 32}, {10, 16}, {10, 8}},
 };
 SingleTune g_jerk[2][kClasses];

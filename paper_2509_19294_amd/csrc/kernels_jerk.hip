@@ -19,6 +19,17 @@
 // tile, then a running sum; TwoSum into hi/lo for the compensated form).
 // Packed source: plain {x,y,z,m},{vx,vy,vz,0}; compensated {hi(x-c),m},
 // {lo(x-c),0},{v-u,0} with c = pos[0], u = vel[0] (FP64 frames).
+//
+// Plain form, one target per lane: J1 is accumulated as sum s v_j and
+// sum s, and v_i times the second is subtracted once per tile, so the three
+// J1 products take the source velocity straight from the scalar registers
+// (two vector-register reads instead of three, which lets more of them
+// dual-issue) for one extra add per pair. The self pair (s = m eps^-3, the
+// largest term of all, which the subtraction would then have to cancel)
+// never enters those sums: the source groups that overlap the wave's own
+// 64 targets use the relative-velocity form, where the self pair's w is 0.
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace nb {
@@ -83,6 +94,8 @@ __global__ __launch_bounds__(256) void pair_jerk_kernel(const float4 *__restrict
   // accumulated quantities: a (3), phi, J1 = sum s w (3), J2 = sum s beta d (3)
   constexpr int NQ = 10;
   constexpr int OW = COMP ? 4 : 2;  // float4 words per partial entry
+  // J1 as sum s v_j - v_i sum s (plain, one target per lane)
+  constexpr bool JS = !COMP && K == 1;
   static_assert(NW % SW == 0, "bad shape");
   __shared__ float X[(SW > 1) ? (SW - 1) * NG * 64 * K * NQ * (COMP ? 2 : 1) : 1];
 
@@ -130,64 +143,95 @@ __global__ __launch_bounds__(256) void pair_jerk_kernel(const float4 *__restrict
   const Quad *Qp = reinterpret_cast<const Quad *>(packed);
   for (int64_t t = J0 + wj * G4; t < J1; t += static_cast<int64_t>(TJ) * SW) {
     const int64_t tend = t + static_cast<int64_t>(TJ) * SW < J1 ? t + static_cast<int64_t>(TJ) * SW : J1;
-    float p[K][NQ];
+    float p[K][NQ + 1];  // [NQ]: sum s (JS only)
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-      for (int c = 0; c < NQ; ++c) p[k][c] = 0.f;
+      for (int c = 0; c < NQ + 1; ++c) p[k][c] = 0.f;
     const uint32_t ngroups = static_cast<uint32_t>((tend - t + STEP - 1) / STEP);
     const Quad *Qt = Qp + ((static_cast<uint64_t>(t) * JW) >> 2);
-    for (uint32_t gi = 0; gi < ngroups; ++gi) {
-      const Quad *Qg = Qt + gi * (STEP * JW / 4);
-      float4 W[G4 * JW];
+    // SPLIT: J1 into sum s v_j and sum s
+    auto groups = [&](uint32_t g0, uint32_t g1, auto split_tag) {
+      constexpr bool SPLIT = decltype(split_tag)::value;
+      for (uint32_t gi = g0; gi < g1; ++gi) {
+        const Quad *Qg = Qt + gi * (STEP * JW / 4);
+        float4 W[G4 * JW];
 #pragma unroll
-      for (int w = 0; w < G4 * JW / 4; ++w) {
-        const Quad qd = Qg[w];
+        for (int w = 0; w < G4 * JW / 4; ++w) {
+          const Quad qd = Qg[w];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) W[w * 4 + c] = qd.v[c];
-      }
+          for (int c = 0; c < 4; ++c) W[w * 4 + c] = qd.v[c];
+        }
 #pragma unroll
-      for (int g = 0; g < G4; ++g) {
-        const float4 H = W[g * JW];
-        const float4 L = COMP ? W[g * JW + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float4 V = W[g * JW + (COMP ? 2 : 1)];
+        for (int g = 0; g < G4; ++g) {
+          const float4 H = W[g * JW];
+          const float4 L = COMP ? W[g * JW + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const float4 V = W[g * JW + (COMP ? 2 : 1)];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          float dx, dy, dz;
-          if constexpr (COMP) {
-            dx = (H.x - xh[k]) + (L.x - xl[k]);
-            dy = (H.y - yh[k]) + (L.y - yl[k]);
-            dz = (H.z - zh[k]) + (L.z - zl[k]);
-          } else {
-            dx = H.x - xh[k];
-            dy = H.y - yh[k];
-            dz = H.z - zh[k];
+          for (int k = 0; k < K; ++k) {
+            float dx, dy, dz;
+            if constexpr (COMP) {
+              dx = (H.x - xh[k]) + (L.x - xl[k]);
+              dy = (H.y - yh[k]) + (L.y - yl[k]);
+              dz = (H.z - zh[k]) + (L.z - zl[k]);
+            } else {
+              dx = H.x - xh[k];
+              dy = H.y - yh[k];
+              dz = H.z - zh[k];
+            }
+            const float wx = V.x - vx[k], wy = V.y - vy[k], wz = V.z - vz[k];
+            float r2 = fmaf(dx, dx, eps2f);
+            r2 = fmaf(dy, dy, r2);
+            r2 = fmaf(dz, dz, r2);
+            float rho = rsq(r2);
+            if constexpr (EPS0) rho = r2 > 0.f ? rho : 0.f;
+            const float rho2 = rho * rho;
+            const float mr = H.w * rho;
+            const float s = mr * rho2;
+            float rv = dx * wx;
+            rv = fmaf(dy, wy, rv);
+            rv = fmaf(dz, wz, rv);
+            const float sb = s * (rv * rho2);
+            p[k][0] = fmaf(s, dx, p[k][0]);
+            p[k][1] = fmaf(s, dy, p[k][1]);
+            p[k][2] = fmaf(s, dz, p[k][2]);
+            p[k][3] += mr;
+            if constexpr (SPLIT) {
+              p[k][4] = fmaf(s, V.x, p[k][4]);
+              p[k][5] = fmaf(s, V.y, p[k][5]);
+              p[k][6] = fmaf(s, V.z, p[k][6]);
+              p[k][NQ] += s;
+            } else {
+              p[k][4] = fmaf(s, wx, p[k][4]);
+              p[k][5] = fmaf(s, wy, p[k][5]);
+              p[k][6] = fmaf(s, wz, p[k][6]);
+            }
+            p[k][7] = fmaf(sb, dx, p[k][7]);
+            p[k][8] = fmaf(sb, dy, p[k][8]);
+            p[k][9] = fmaf(sb, dz, p[k][9]);
           }
-          const float wx = V.x - vx[k], wy = V.y - vy[k], wz = V.z - vz[k];
-          float r2 = fmaf(dx, dx, eps2f);
-          r2 = fmaf(dy, dy, r2);
-          r2 = fmaf(dz, dz, r2);
-          float rho = rsq(r2);
-          if constexpr (EPS0) rho = r2 > 0.f ? rho : 0.f;
-          const float rho2 = rho * rho;
-          const float mr = H.w * rho;
-          const float s = mr * rho2;
-          float rv = dx * wx;
-          rv = fmaf(dy, wy, rv);
-          rv = fmaf(dz, wz, rv);
-          const float sb = s * (rv * rho2);
-          p[k][0] = fmaf(s, dx, p[k][0]);
-          p[k][1] = fmaf(s, dy, p[k][1]);
-          p[k][2] = fmaf(s, dz, p[k][2]);
-          p[k][3] += mr;
-          p[k][4] = fmaf(s, wx, p[k][4]);
-          p[k][5] = fmaf(s, wy, p[k][5]);
-          p[k][6] = fmaf(s, wz, p[k][6]);
-          p[k][7] = fmaf(sb, dx, p[k][7]);
-          p[k][8] = fmaf(sb, dy, p[k][8]);
-          p[k][9] = fmaf(sb, dz, p[k][9]);
         }
       }
+    };
+    if constexpr (JS) {
+      // groups [ga, gb) overlap the wave's own targets [iw, iw + 64): they
+      // keep the relative-velocity form, so the self pair adds exactly 0
+      const int64_t iw = i0 + wg * 64;
+      const int64_t lo = iw - G4 - t, hi = iw + 64 - t;
+      int64_t ga = lo < 0 ? 0 : lo / STEP + 1;
+      int64_t gb = hi <= 0 ? 0 : (hi + STEP - 1) / STEP;
+      ga = ga < ngroups ? ga : ngroups;
+      gb = gb < ga ? ga : (gb < ngroups ? gb : ngroups);
+      groups(0, static_cast<uint32_t>(ga), std::true_type{});
+      groups(static_cast<uint32_t>(ga), static_cast<uint32_t>(gb), std::false_type{});
+      groups(static_cast<uint32_t>(gb), ngroups, std::true_type{});
+    } else {
+      groups(0, ngroups, std::false_type{});
+    }
+    if constexpr (JS) {
+      p[0][4] = fmaf(-vx[0], p[0][NQ], p[0][4]);
+      p[0][5] = fmaf(-vy[0], p[0][NQ], p[0][5]);
+      p[0][6] = fmaf(-vz[0], p[0][NQ], p[0][6]);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k)
