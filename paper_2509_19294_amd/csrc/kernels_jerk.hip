@@ -17,14 +17,19 @@
 // splitting the sources (combined through LDS in wave order), a grid j-split
 // combined in FP64 by a second kernel. Sums are two-level (plain FP32 per
 // tile, then a running sum; TwoSum into hi/lo for the compensated form).
-// Packed source: plain {x,y,z,m},{vx,vy,vz,0}; compensated {hi(x-c),m},
-// {lo(x-c),0},{v-u,0} with c = pos[0], u = vel[0] (FP64 frames).
+// Packed source: plain {x,y,z,m},{v-u,0}; compensated {hi(x-c),m},
+// {lo(x-c),0},{v-u,0} with c = pos[0], u = vel[0] (FP64 frames). The jerk
+// depends on velocity differences only, so both forms take velocities
+// relative to particle 0's: their rounding, and the cancellation of the split
+// J1 sum below, then scale with the spread of the velocities, not with a
+// bulk motion of the system.
 //
 // Plain form, one target per lane: J1 is accumulated as sum s v_j and
 // sum s, and v_i times the second is subtracted once per tile, so the three
 // J1 products take the source velocity straight from the scalar registers
 // (two vector-register reads instead of three, which lets more of them
-// dual-issue) for one extra add per pair. The self pair (s = m eps^-3, the
+// dual-issue) for one extra add per pair; what v_i sum s cancels is of the
+// size of |v_j - u| sum s. The self pair (s = m eps^-3, the
 // largest term of all, which the subtraction would then have to cancel)
 // never enters those sums: the source groups that overlap the wave's own
 // 64 targets use the relative-velocity form, where the self pair's w is 0.
@@ -67,8 +72,8 @@ __global__ __launch_bounds__(256) void pack_jerk_kernel(const double *__restrict
   } else {
     o[0] = make_float4(static_cast<float>(pos[3 * i]), static_cast<float>(pos[3 * i + 1]),
                        static_cast<float>(pos[3 * i + 2]), m);
-    o[1] = make_float4(static_cast<float>(vel[3 * i]), static_cast<float>(vel[3 * i + 1]),
-                       static_cast<float>(vel[3 * i + 2]), 0.f);
+    o[1] = make_float4(static_cast<float>(vel[3 * i] - vel[0]), static_cast<float>(vel[3 * i + 1] - vel[1]),
+                       static_cast<float>(vel[3 * i + 2] - vel[2]), 0.f);
   }
 }
 
