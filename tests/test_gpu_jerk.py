@@ -199,6 +199,27 @@ def test_plummer_64k_full_oracle(variant):
     print(f"plummer_64k jerk {variant}: acc rel-rms {e[0]:.3e} jerk rel-rms {e[1]:.3e} paper metric {e[2]:.3e}")
 
 
+@pytest.mark.parametrize("workload,variant", [("plummer_256k", "plain"), ("plummer_256k", "comp"),
+                                              ("kroupa_1m", "comp")])
+def test_large_subsample(workload, variant):
+    """N = 262,144 (eps = 0.002) and N = 1,048,576 with Kroupa masses
+    (eps = 0.001), in the tuned launch (the compensated form's near/far
+    shapes, the plain form's split J1 sum): 4096 strided targets against all
+    sources in the C oracle."""
+    pos, vel, mass, spec = ics.workload(workload)
+    eps = spec["eps"]
+    tgt = orc.subsample_targets(len(mass), 4096)
+    got = tuple(x[tgt] for x in gpu_accel_jerk(pos, vel, mass, eps, variant))
+    exact = ocpu.accel_jerk(pos, vel, mass, eps, targets=tgt)
+    if variant == "comp":
+        form = exact
+    else:
+        v0 = vel[0]
+        form = ocpu.accel_jerk(f32(pos), v0 + f32(vel - v0), f32(mass), eps, targets=tgt)
+    e = check(got, (exact, form), (workload, variant))
+    print(f"{workload} {variant}: acc {e[0]:.3e} jerk {e[1]:.3e} jerk paper metric {e[2]:.3e}")
+
+
 @pytest.mark.parametrize("variant", ["plain", "comp"])
 def test_hermite_plummer_1k(variant):
     pos, vel, mass, spec = ics.workload("plummer_1k")
