@@ -113,15 +113,15 @@ int size_class(int64_t n) {
 // 10..20 for the plain and compensated forms; smaller classes take class 10's
 // entry and larger ones class 20's. Batched modes for classes 8..13.
 const SingleTune kTuned[2][11] = {
-    {{5, 4}, {5, 8}, {4, 4}, {4, 4}, {18, 16}, {18, 16}, {18, 32}, {14, 32}, {14, 32}, {14, 8}, {14, 8}},
-    {{5, 4}, {5, 8}, {5, 8}, {0, 16}, {18, 16}, {18, 16}, {9, 32}, {23, 32}, {23, 32}, {23, 8}, {23, 8}},
+    {{5, 4}, {5, 8}, {5, 8}, {4, 8}, {15, 16}, {15, 16}, {15, 16}, {13, 16}, {13, 32}, {13, 8}, {15, 2}},
+    {{5, 4}, {5, 8}, {4, 4}, {0, 16}, {15, 16}, {15, 16}, {15, 32}, {15, 32}, {23, 32}, {23, 8}, {23, 8}},
 };
 const int kTunedBatched[2][6] = {{8, 4, 4, 4, 4, 4}, {1, 4, 4, 4, 4, 4}};
 // Acceleration + jerk kernel: {shape, split} per size class 10..20, measured
 // on MI355X by the same autotuner (Plummer spheres of 2^c particles,
 // eps = 0.01; split 0 would select the rule of jerk_default_split).
 const SingleTune kTunedJerk[2][11] = {
-    {{8, 1}, {8, 2}, {8, 4}, {2, 8}, {2, 16}, {2, 16}, {2, 32}, {0, 32}, {0, 32}, {0, 16}, {0, 8}},
+    {{8, 1}, {8, 2}, {8, 4}, {2, 8}, {2, 16}, {2, 32}, {2, 32}, {2, 32}, {1, 32}, {0, 16}, {2, 2}},
     {{2, 1}, {2, 2}, {2, 4}, {2, 8}, {2, 16}, {10, 32}, {10, 32}, {11, 32}, {10, 32}, {10, 16}, {10, 8}},
 };
 SingleTune g_jerk[2][kClasses];

@@ -472,8 +472,27 @@ __device__ __forceinline__ void smem_block(const float4 *__restrict__ packed, in
     // control stays on the scalar unit.
     const uint32_t ngroups = static_cast<uint32_t>((tend - t + STEP - 1) / STEP);
     const Quad *Qt = Qp + ((static_cast<uint64_t>(t) * JW) >> 2);
+    // PF: the next group's scalar loads are issued before this group's pairs
+    // (one target per lane, and a group of at most 32 scalar registers, so
+    // that two of them fit)
+    constexpr int NQD = G * JW / 4;
+    constexpr bool PF = K == 1 && NQD <= 2;
+    Quad cur[NQD];
+    if constexpr (PF) {
+      if (ngroups > 0) {
+#pragma unroll
+        for (int q = 0; q < NQD; ++q) cur[q] = Qt[q];
+      }
+    }
     for (uint32_t gi = 0; gi < ngroups; ++gi) {
-      const Quad *Qg = Qt + gi * (STEP * JW / 4);
+      Quad nxt[NQD];
+      if constexpr (PF) {
+        const uint32_t gn = gi + 1 < ngroups ? gi + 1 : gi;
+        const Quad *Qn = Qt + gn * (STEP * JW / 4);
+#pragma unroll
+        for (int q = 0; q < NQD; ++q) nxt[q] = Qn[q];
+      }
+      const Quad *Qg = PF ? cur : Qt + gi * (STEP * JW / 4);
       float4 H[G], L[G];
       if constexpr (COMP) {
 #pragma unroll
@@ -521,6 +540,10 @@ __device__ __forceinline__ void smem_block(const float4 *__restrict__ packed, in
           p[k][2] = fmaf(s, dz, p[k][2]);
           p[k][3] += mr;
         }
+      }
+      if constexpr (PF) {
+#pragma unroll
+        for (int q = 0; q < NQD; ++q) cur[q] = nxt[q];
       }
     }
 #pragma unroll

@@ -156,10 +156,27 @@ __global__ __launch_bounds__(256) void pair_jerk_kernel(const float4 *__restrict
     const uint32_t ngroups = static_cast<uint32_t>((tend - t + STEP - 1) / STEP);
     const Quad *Qt = Qp + ((static_cast<uint64_t>(t) * JW) >> 2);
     // SPLIT: J1 into sum s v_j and sum s
+    // PF: the next group's scalar loads are issued before this group's pairs
+    // (one target per lane, groups of at most 32 scalar registers)
+    constexpr int NQD = G4 * JW / 4;
+    constexpr bool PF = K == 1 && NQD <= 2;
     auto groups = [&](uint32_t g0, uint32_t g1, auto split_tag) {
       constexpr bool SPLIT = decltype(split_tag)::value;
+      Quad cur[NQD];
+      if constexpr (PF) {
+        if (g0 < g1) {
+#pragma unroll
+          for (int q = 0; q < NQD; ++q) cur[q] = Qt[g0 * (STEP * JW / 4) + q];
+        }
+      }
       for (uint32_t gi = g0; gi < g1; ++gi) {
-        const Quad *Qg = Qt + gi * (STEP * JW / 4);
+        Quad nxt[NQD];
+        if constexpr (PF) {
+          const uint32_t gn = gi + 1 < g1 ? gi + 1 : gi;
+#pragma unroll
+          for (int q = 0; q < NQD; ++q) nxt[q] = Qt[gn * (STEP * JW / 4) + q];
+        }
+        const Quad *Qg = PF ? cur : Qt + gi * (STEP * JW / 4);
         float4 W[G4 * JW];
 #pragma unroll
         for (int w = 0; w < G4 * JW / 4; ++w) {
@@ -215,6 +232,10 @@ __global__ __launch_bounds__(256) void pair_jerk_kernel(const float4 *__restrict
             p[k][8] = fmaf(sb, dy, p[k][8]);
             p[k][9] = fmaf(sb, dz, p[k][9]);
           }
+        }
+        if constexpr (PF) {
+#pragma unroll
+          for (int q = 0; q < NQD; ++q) cur[q] = nxt[q];
         }
       }
     };
