@@ -862,11 +862,13 @@ __device__ __forceinline__ void batched_item(const Item &d, const double *__rest
 // contiguous, heaviest-first segment of the plan's work list) from its own
 // counter until none is left.
 template <int MODE, bool COMP>
-__global__ __launch_bounds__(256) void pair_batched_kernel(
-    const double *__restrict__ pos, const double *__restrict__ mass,
-    const float4 *__restrict__ packed, const Item *__restrict__ items, int32_t n_items,
-    const double *__restrict__ eps_k, double G, int *__restrict__ counter,
-    double *__restrict__ acc, double *__restrict__ pot) {
+__device__ __forceinline__ void batched_loop(const double *__restrict__ pos,
+                                             const double *__restrict__ mass,
+                                             const float4 *__restrict__ packed,
+                                             const Item *__restrict__ items, int32_t n_items,
+                                             const double *__restrict__ eps_k, double G,
+                                             int *__restrict__ counter, double *__restrict__ acc,
+                                             double *__restrict__ pot) {
   __shared__ float4 lds[batched_lds_float4<MODE, COMP>()];
   __shared__ int s_item;
   OutArgs o{};
@@ -888,6 +890,28 @@ __global__ __launch_bounds__(256) void pair_batched_kernel(
       batched_item<MODE, COMP, false>(d, pos, mass, packed, eps2f, lds, o);
     __syncthreads();
   }
+}
+
+// LDS modes: the compiler's own register allocation.
+template <int MODE, bool COMP>
+__global__ __launch_bounds__(256) void pair_batched_kernel(
+    const double *__restrict__ pos, const double *__restrict__ mass,
+    const float4 *__restrict__ packed, const Item *__restrict__ items, int32_t n_items,
+    const double *__restrict__ eps_k, double G, int *__restrict__ counter,
+    double *__restrict__ acc, double *__restrict__ pot) {
+  batched_loop<MODE, COMP>(pos, mass, packed, items, n_items, eps_k, G, counter, acc, pot);
+}
+
+// Scalar-stream modes: held to 8 waves per SIMD (the compensated form's item
+// loop otherwise takes about 100 SGPRs, which leaves room for 7; at 8 it fits
+// in 72 with no spills).
+template <int MODE, bool COMP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void pair_batched_smem_kernel(
+    const double *__restrict__ pos, const double *__restrict__ mass,
+    const float4 *__restrict__ packed, const Item *__restrict__ items, int32_t n_items,
+    const double *__restrict__ eps_k, double G, int *__restrict__ counter,
+    double *__restrict__ acc, double *__restrict__ pot) {
+  batched_loop<MODE, COMP>(pos, mass, packed, items, n_items, eps_k, G, counter, acc, pot);
 }
 
 // Slot-layout pack of a batched plan: slot s holds source slot_src[s] (or
@@ -928,12 +952,21 @@ static hipError_t launch_mode(const BatchedArgs &b, int m, const double *pos, co
                              double *pot, hipStream_t st) {
   const Item *it = b.items + b.seg_begin[m];
   const int32_t cnt = b.seg_end[m] - b.seg_begin[m];
-  if (b.comp)
-    pair_batched_kernel<MODE, true><<<b.grid[m], 256, 0, st>>>(pos, mass, packed, it, cnt, b.eps_k,
-                                                                G, counters + m, acc, pot);
-  else
-    pair_batched_kernel<MODE, false><<<b.grid[m], 256, 0, st>>>(pos, mass, packed, it, cnt, b.eps_k,
-                                                                 G, counters + m, acc, pot);
+  if constexpr (kBatchedSmem[MODE] != 0) {
+    if (b.comp)
+      pair_batched_smem_kernel<MODE, true><<<b.grid[m], 256, 0, st>>>(pos, mass, packed, it, cnt,
+                                                                       b.eps_k, G, counters + m, acc, pot);
+    else
+      pair_batched_smem_kernel<MODE, false><<<b.grid[m], 256, 0, st>>>(pos, mass, packed, it, cnt,
+                                                                        b.eps_k, G, counters + m, acc, pot);
+  } else {
+    if (b.comp)
+      pair_batched_kernel<MODE, true><<<b.grid[m], 256, 0, st>>>(pos, mass, packed, it, cnt, b.eps_k,
+                                                                  G, counters + m, acc, pot);
+    else
+      pair_batched_kernel<MODE, false><<<b.grid[m], 256, 0, st>>>(pos, mass, packed, it, cnt, b.eps_k,
+                                                                   G, counters + m, acc, pot);
+  }
   return hipGetLastError();
 }
 
@@ -970,9 +1003,13 @@ hipError_t launch_pair_batched(const BatchedArgs &b, const double *pos, const do
 template <int MODE>
 static int occupancy(bool comp) {
   int per = 0;
-  const hipError_t e =
-      comp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pair_batched_kernel<MODE, true>, 256, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pair_batched_kernel<MODE, false>, 256, 0);
+  hipError_t e;
+  if constexpr (kBatchedSmem[MODE] != 0)
+    e = comp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pair_batched_smem_kernel<MODE, true>, 256, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pair_batched_smem_kernel<MODE, false>, 256, 0);
+  else
+    e = comp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pair_batched_kernel<MODE, true>, 256, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pair_batched_kernel<MODE, false>, 256, 0);
   return e == hipSuccess ? per : 0;
 }
 
