@@ -1,4 +1,4 @@
-// Device helpers shared by the pair kernels (kernels.hip, kernels_sym.hip).
+// Device helpers shared by the pair kernels (csrc/kernels*.hip).
 #pragma once
 
 #include "nbody_internal.h"
