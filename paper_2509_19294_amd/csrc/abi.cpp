@@ -1,6 +1,6 @@
 // C ABI of libnbody.so (declared in include/nbody.h): host-side validation,
 // workspace layout, tuning lookup, kernel dispatch, batched plans and their
-// HIP graphs. Every device-side step runs in the kernels of kernels.hip.
+// HIP graphs. Every device-side step runs in the kernels of csrc/kernels*.hip.
 #include "nbody.h"
 
 #include <algorithm>

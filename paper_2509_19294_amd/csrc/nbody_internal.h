@@ -1,5 +1,5 @@
 // Internal interface between the C ABI (abi.cpp) and the HIP kernels
-// (kernels.hip). Not installed; the public contract is include/nbody.h.
+// (kernels*.hip). Not installed; the public contract is include/nbody.h.
 #pragma once
 
 #include <hip/hip_runtime.h>
