@@ -8,14 +8,14 @@
 // its FP64 frame c. Source tiles of 256 ordered particles are staged in
 // LDS relative to c, and each tile takes one of two paths, the same for the
 // whole block:
-//   * near (the tile's box lies closer to B than D / 2): double-single
+//   * near (the tile's box lies closer to B than D / 4): double-single
 //     staging, separation (hi_j - hi_i) + (lo_j - lo_i), as in the
 //     compensated form;
-//   * far (box distance >= D / 2): hi parts only, separation hi_j - hi_i.
+//   * far (box distance >= D / 4): hi parts only, separation hi_j - hi_i.
 // Far-path error: with |x_i - c| <= D / 2 and |x_j - c| <= |d| + D / 2,
 // rounding the two offsets to FP32 and subtracting moves d by at most
-// u (|x_i - c| + |x_j - c| + |d|) <= u (2 |d| + D) <= 4 u |d|, since every
-// pair of a far tile has |d| >= D / 2 (u = 2^-24): a few units of FP32
+// u (|x_i - c| + |x_j - c| + |d|) <= u (2 |d| + D) <= 6 u |d|, since every
+// pair of a far tile has |d| >= D / 4 (u = 2^-24): a few units of FP32
 // rounding of the separation itself, independent of where the system sits,
 // at the plain form's 13 operations per pair. The self pair falls in a near
 // tile (its box overlaps B) unless D = 0, where both offsets are exactly 0.
@@ -81,8 +81,8 @@ __global__ __launch_bounds__(256) void pair_nf_kernel(const double *__restrict__
     }
   }
   const double cx = 0.5 * (bl[0] + bh[0]), cy = 0.5 * (bl[1] + bh[1]), cz = 0.5 * (bl[2] + bh[2]);
-  // far threshold: (D / 2)^2
-  const double D2 = 0.25 * ((bh[0] - bl[0]) * (bh[0] - bl[0]) + (bh[1] - bl[1]) * (bh[1] - bl[1]) +
+  // far threshold: (D / 4)^2
+  const double D2 = 0.0625 * ((bh[0] - bl[0]) * (bh[0] - bl[0]) + (bh[1] - bl[1]) * (bh[1] - bl[1]) +
                             (bh[2] - bl[2]) * (bh[2] - bl[2]));
 
   float xh[K], yh[K], zh[K], xl[K], yl[K], zl[K], mi[K];

@@ -6,8 +6,8 @@
 // centre of its box (diagonal D) as its FP64 position frame c and the
 // velocity of its first target as its velocity frame u. Each 256-source tile
 // is staged in LDS as {hi(x - c), m}, {lo(x - c), 0}, {fp32(v - u), 0};
-// source tiles at least D / 2 from the block's box skip the lo parts (the
-// separation then carries at most 4 u |d| of error, see kernels_nf.hip).
+// source tiles at least D / 4 from the block's box skip the lo parts (the
+// separation then carries at most 6 u |d| of error, see kernels_nf.hip).
 // The relative velocity is always fp32(v_j - u) - fp32(v_i - u), rounded
 // relative to the velocities' spread. Per pair the jerk arithmetic is that of
 // kernels_jerk.hip (acceleration, potential, J1 = sum s w, J2 = sum s beta
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void pair_nf_jerk_kernel(const double *__restr
   }
   const double cx = 0.5 * (bl[0] + bh[0]), cy = 0.5 * (bl[1] + bh[1]), cz = 0.5 * (bl[2] + bh[2]);
   const double ux = svel[3 * i0], uy = svel[3 * i0 + 1], uz = svel[3 * i0 + 2];
-  const double D2 = 0.25 * ((bh[0] - bl[0]) * (bh[0] - bl[0]) + (bh[1] - bl[1]) * (bh[1] - bl[1]) +
+  const double D2 = 0.0625 * ((bh[0] - bl[0]) * (bh[0] - bl[0]) + (bh[1] - bl[1]) * (bh[1] - bl[1]) +
                             (bh[2] - bl[2]) * (bh[2] - bl[2]));
 
   float xh[K], yh[K], zh[K], xl[K], yl[K], zl[K], vx[K], vy[K], vz[K], mi[K];
