@@ -48,7 +48,7 @@ DEFAULT_VARIANT = {"plummer_1k": "plain", "plummer_64k": "plain", "plummer_256k"
 MEASURED_TRAFFIC = {
     ("plummer_64k", "plain", 15, 16): 32541696,
     # near/far compensated kernel, configuration 23
-    ("plummer_256k", "comp", 23, 32): 332125184,
+    ("plummer_256k", "comp", 23, 32): 331932262,
     # acceleration + jerk kernel (bench.py --hermite): shape 2, split 32
     ("plummer_64k", "plain", "jerk", 2, 32): 98617549,
 }

@@ -61,7 +61,7 @@ typedef int32_t nbody_status;
                                orders the particles spatially (internally; results stay at
                                the caller's indices) and source tiles far from a block
                                drop the lo parts, which keeps every separation within
-                               4 ulps of its own size */
+                               6 ulps of its own size */
 
 /* One diagnostics row (float64), written after every step by nbody_step. */
 #define NBODY_DIAG_LEN 16
