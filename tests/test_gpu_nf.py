@@ -95,6 +95,13 @@ def test_distant_clusters_take_far_tiles(cfg):
     ra, rp = orc.accel_pot(pos, mass, 0.001)
     a, p = nf_accel(pos, mass, 0.001, cfg, 1)
     check(a, p, ra, rp, (cfg, "clusters"))
+    # the far path's bound (separations within 6 u |d|, u = 2^-24) keeps the
+    # result near FP32 rounding (measured 1.0e-7 to 2.8e-7): far tiles
+    # staged relative to a frame in the other cluster, 100 away, would round
+    # every intra-cluster separation to about u 100, 1e-5 of a typical one
+    e = orc.rel_rms(a, ra)
+    print(f"distant clusters cfg {cfg}: rel-rms {e:.3e} max-rel {orc.max_rel(a, ra):.3e}")
+    assert e <= 1e-6, (cfg, e)
 
 
 @pytest.mark.parametrize("cfg", NF_CFGS)
