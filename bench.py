@@ -320,7 +320,57 @@ def cpu_baseline(pos, mass, eps, budget_s, vel=None):
         "cores": threads,
         "kind": "oracle",
         "sample": f"{sample} ({pairs:.3e} FP64 pairs in {el:.1f} s; {what}; C + OpenMP, {threads} threads)",
+        "cpu_model": _cpu_model(),
+        "numpy_single_thread": _numpy_oracle_rate(pos, mass, eps, vel),
     }, gate, refs
+
+
+def _cpu_model():
+    """The host CPU's model name, from /proc/cpuinfo (None if unreadable)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _numpy_oracle_rate(pos, mass, eps, vel=None, min_s=0.2):
+    """Rate of the numpy oracle (one thread) on strided targets against all
+    sources, for information beside the C oracle's."""
+    from oracle import oracle as orc
+
+    n = len(mass)
+    k = min(n, 4)
+    while True:
+        tgt = orc.subsample_targets(n, k)
+        t0 = time.perf_counter()
+        if vel is None:
+            orc.accel_pot(pos, mass, eps, targets=tgt)
+        else:
+            orc.accel_jerk(pos, vel, mass, eps, targets=tgt)
+        el = time.perf_counter() - t0
+        if el >= min_s or k >= n:
+            break
+        k = min(n, k * 4)
+    return {"value": round(len(tgt) * n / max(el, 1e-9) / 1e9, 4), "unit": "G pair-interactions/s",
+            "sample": f"{len(tgt)} strided targets x {n} sources"}
+
+
+def device_info():
+    """Name, compute units and temperatures of cuda:0 at the end of a run
+    (temperatures from the system-management library, None if unreadable)."""
+    import torch
+
+    from paper_2509_19294_amd import energy
+
+    props = torch.cuda.get_device_properties(0)
+    info = {"name": props.name, "arch": getattr(props, "gcnArchName", None),
+            "compute_units": props.multi_processor_count}
+    info.update(energy.temperatures(0))
+    return info
 
 
 def copy_calibration(mib: int = 1024, reps: int = 5):
@@ -525,6 +575,10 @@ def main():
             "flops_per_interaction": flops,
         },
     }
+    try:
+        out["device"] = device_info()
+    except Exception as e:  # informational only
+        out["device"] = {"note": f"device information unavailable: {e}"}
 
     if not args.no_cpu_baseline:
         from oracle import oracle as orc

@@ -90,6 +90,30 @@ def _open_handle(device_index: int):
     return smi, chosen, notes
 
 
+def temperatures(device_index: int = 0) -> dict:
+    """Edge and hotspot temperatures (degrees C) of a torch device from the
+    system-management library; None for a reading it cannot give."""
+    out = {"temp_edge_c": None, "temp_hotspot_c": None}
+    smi, handle, notes = _open_handle(device_index)
+    if smi is None:
+        return out
+    try:
+        if handle is not None:
+            types = smi.AmdSmiTemperatureType
+            metric = smi.AmdSmiTemperatureMetric.CURRENT
+            for key, name in (("temp_edge_c", "EDGE"), ("temp_hotspot_c", "HOTSPOT")):
+                try:
+                    out[key] = float(smi.amdsmi_get_temp_metric(handle, getattr(types, name), metric))
+                except Exception:
+                    pass
+    finally:
+        try:
+            smi.amdsmi_shut_down()
+        except Exception:
+            pass
+    return out
+
+
 class EnergyMeter:
     """Context manager measuring GPU and host energy over its body."""
 
