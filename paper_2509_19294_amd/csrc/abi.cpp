@@ -114,7 +114,7 @@ int size_class(int64_t n) {
 // entry and larger ones class 20's. Batched modes for classes 8..13.
 const SingleTune kTuned[2][11] = {
     {{5, 4}, {5, 8}, {5, 8}, {4, 8}, {15, 16}, {15, 16}, {15, 16}, {13, 16}, {13, 32}, {13, 8}, {15, 2}},
-    {{5, 4}, {5, 8}, {4, 4}, {0, 16}, {15, 16}, {15, 16}, {15, 32}, {15, 32}, {23, 32}, {23, 8}, {23, 8}},
+    {{5, 4}, {5, 8}, {4, 4}, {0, 16}, {15, 16}, {15, 32}, {15, 32}, {23, 32}, {23, 32}, {23, 8}, {23, 8}},
 };
 const int kTunedBatched[2][6] = {{8, 4, 4, 4, 4, 4}, {1, 4, 4, 4, 4, 4}};
 // Acceleration + jerk kernel: {shape, split} per size class 10..20, measured
