@@ -175,6 +175,8 @@ __global__ __launch_bounds__(256) void pair_nf_jerk_kernel(const double *__restr
       for (int c = 0; c < kNQ; ++c) p[k][c] = 0.f;
 
     // one pair: d (separation), w (relative velocity), m (source mass)
+    // one target per lane: a shallower unroll keeps more waves resident
+    constexpr int UNR = K == 1 ? 2 : 4;
     auto pair = [&](int k, float dx, float dy, float dz, const float4 &V, float m) {
       const float wx = V.x - vx[k], wy = V.y - vy[k], wz = V.z - vz[k];
       float r2 = fmaf(dx, dx, eps2f);
@@ -202,14 +204,14 @@ __global__ __launch_bounds__(256) void pair_nf_jerk_kernel(const double *__restr
     };
 
     if (far_cur) {
-#pragma unroll 4
+#pragma unroll UNR
       for (int jj = wj; jj < kNfjTile; jj += SW) {
         const float4 H = T[3 * jj], V = T[3 * jj + 2];
 #pragma unroll
         for (int k = 0; k < K; ++k) pair(k, H.x - xh[k], H.y - yh[k], H.z - zh[k], V, H.w);
       }
     } else {
-#pragma unroll 4
+#pragma unroll UNR
       for (int jj = wj; jj < kNfjTile; jj += SW) {
         const float4 H = T[3 * jj], L = T[3 * jj + 1], V = T[3 * jj + 2];
 #pragma unroll
