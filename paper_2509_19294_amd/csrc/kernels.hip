@@ -640,7 +640,8 @@ __global__ __launch_bounds__(256) void pair_smem_kernel(const float4 *__restrict
 
 // Compiled single-system configurations: {block, k, ls, sw, tile, smem}
 // (smem: 0 = LDS tiles, 1 = scalar stream with 4-source groups, 2 = with
-// 8-source groups).
+// 8-source groups, 3 = near/far on the spatial order, 4 = near/far with the
+// frame stored by the ordering pass).
 static const PairCfg kSingle[] = {
     {256, 1, 1, 1, 256, 0},   // 0
     {256, 2, 1, 1, 256, 0},   // 1
@@ -666,6 +667,7 @@ static const PairCfg kSingle[] = {
     {256, 4, 1, 4, 256, 3},   // 21: near/far, 256 i, four waves split the sources
     {256, 4, 1, 2, 256, 3},   // 22: near/far, 512 i, two waves per target group
     {256, 2, 1, 2, 256, 3},   // 23: near/far, 256 i, two waves per target group
+    {256, 2, 1, 2, 256, 4},   // 24: as 23, frame stored by the ordering pass, 6 waves per SIMD
 };
 int single_cfg_count() { return static_cast<int>(sizeof(kSingle) / sizeof(kSingle[0])); }
 int single_cfg_count(bool comp) { return comp ? single_cfg_count() : 19; }
@@ -731,7 +733,7 @@ hipError_t launch_pair_single(int cfg, bool comp, const double *pos, const doubl
   if (n <= 0) return hipSuccess;
   if (cfg < 0 || cfg >= single_cfg_count()) return hipErrorInvalidValue;
   const PairCfg &c = kSingle[cfg];
-  if (c.smem == 3) return hipErrorInvalidValue;  // near/far: launch_order + launch_pair_nf
+  if (c.smem >= 3) return hipErrorInvalidValue;  // near/far: launch_order + launch_pair_nf
   const int64_t ib = cfg_iblock(c);
   const int64_t nblk = (n + ib - 1) / ib;
   if (split < 1) split = 1;

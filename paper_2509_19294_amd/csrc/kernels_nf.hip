@@ -44,14 +44,27 @@ constexpr int nf_lds_float4() {
   return tiles > combine ? tiles : combine;
 }
 
-template <int K, int SW, bool EPS0>
-__global__ __launch_bounds__(256) void pair_nf_kernel(const double *__restrict__ spos,
+// SF: the block covers one box group and reads its box, centre and
+// threshold as the ordering pass wrote them (uniform loads, which stay in
+// scalar registers), and the compiler is held to 6 waves per SIMD, which the
+// two-target shape then reaches without spills (94 -> 74 VGPRs). Otherwise
+// the block computes them and the compiler picks the occupancy.
+template <bool SF>
+constexpr int nf_waves() {
+  return SF ? 6 : 1;
+}
+
+template <int K, int SW, bool SF, bool EPS0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(nf_waves<SF>()))) void
+pair_nf_kernel(const double *__restrict__ spos,
                                                       const double *__restrict__ smass,
-                                                      const double *__restrict__ box, int64_t n,
+                                                      const double *__restrict__ box,
+                                                      const double *__restrict__ bfr, int64_t n,
                                                       float eps2f, int64_t split_len, NfOut o) {
   constexpr int NG = 4 / SW;          // target groups of 64 lanes per block
   constexpr int IB = NG * 64 * K;
   static_assert(IB % kOrderGroup == 0 && 4 % SW == 0, "block shape");
+  static_assert(!SF || IB == kOrderGroup, "stored frame: one box group per block");
   __shared__ float4 smem[nf_lds_float4<K, SW>()];
   float4 (*lds)[2 * kNfTile] = reinterpret_cast<float4 (*)[2 * kNfTile]>(smem);
   const int tid = threadIdx.x;
@@ -66,7 +79,8 @@ __global__ __launch_bounds__(256) void pair_nf_kernel(const double *__restrict__
   // the block's box: union of its groups' boxes; the frame is its centre
   double bl[3], bh[3];
   {
-    const int64_t g0 = i0 / kOrderGroup, g1 = (i1 - 1) / kOrderGroup;
+    const int64_t g0 = i0 / kOrderGroup;
+    const int64_t g1 = SF ? g0 : (i1 - 1) / kOrderGroup;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       bl[c] = box[6 * g0 + c];
@@ -80,10 +94,15 @@ __global__ __launch_bounds__(256) void pair_nf_kernel(const double *__restrict__
       }
     }
   }
-  const double cx = 0.5 * (bl[0] + bh[0]), cy = 0.5 * (bl[1] + bh[1]), cz = 0.5 * (bl[2] + bh[2]);
+  const int64_t gb = i0 / kOrderGroup;
+  const double cx = SF ? bfr[4 * gb] : 0.5 * (bl[0] + bh[0]);
+  const double cy = SF ? bfr[4 * gb + 1] : 0.5 * (bl[1] + bh[1]);
+  const double cz = SF ? bfr[4 * gb + 2] : 0.5 * (bl[2] + bh[2]);
   // far threshold: (D / 4)^2
-  const double D2 = 0.0625 * ((bh[0] - bl[0]) * (bh[0] - bl[0]) + (bh[1] - bl[1]) * (bh[1] - bl[1]) +
-                            (bh[2] - bl[2]) * (bh[2] - bl[2]));
+  const double D2 = SF ? bfr[4 * gb + 3]
+                       : 0.0625 * ((bh[0] - bl[0]) * (bh[0] - bl[0]) +
+                                   (bh[1] - bl[1]) * (bh[1] - bl[1]) +
+                                   (bh[2] - bl[2]) * (bh[2] - bl[2]));
 
   float xh[K], yh[K], zh[K], xl[K], yl[K], zl[K], mi[K];
   int64_t iidx[K];
@@ -317,21 +336,23 @@ __global__ __launch_bounds__(256) void combine_nf_kernel(const float4 *__restric
   }
 }
 
-template <int K, int SW>
+template <int K, int SW, bool SF = false>
 hipError_t launch_nf_t(bool eps0, dim3 grid, const OrderWs &w, int64_t n, float eps2f,
                        int64_t split_len, const NfOut &o, hipStream_t st) {
   if (eps0)
-    pair_nf_kernel<K, SW, true><<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, n, eps2f, split_len, o);
+    pair_nf_kernel<K, SW, SF, true>
+        <<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, w.bfr, n, eps2f, split_len, o);
   else
-    pair_nf_kernel<K, SW, false><<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, n, eps2f, split_len, o);
+    pair_nf_kernel<K, SW, SF, false>
+        <<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, w.bfr, n, eps2f, split_len, o);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_pair_nf(int k, int sw, const OrderWs &w, int64_t n, double eps, double G,
-                          int split, double *acc, double *pot, float4 *part, hipStream_t stream,
-                          hipEvent_t after_pair) {
+hipError_t launch_pair_nf(int k, int sw, bool sf, const OrderWs &w, int64_t n, double eps,
+                          double G, int split, double *acc, double *pot, float4 *part,
+                          hipStream_t stream, hipEvent_t after_pair) {
   if (n <= 0) return hipSuccess;
   if (split < 1) split = 1;
   if (split > max_split(n)) split = max_split(n);
@@ -353,7 +374,10 @@ hipError_t launch_pair_nf(int k, int sw, const OrderWs &w, int64_t n, double eps
   }
   dim3 grid(static_cast<unsigned>(nblk), static_cast<unsigned>(split));
   hipError_t e;
-  if (k == 2 && sw == 1) e = launch_nf_t<2, 1>(eps0, grid, w, n, eps2f, split_len, o, stream);
+  if (sf) {
+    if (k == 2 && sw == 2) e = launch_nf_t<2, 2, true>(eps0, grid, w, n, eps2f, split_len, o, stream);
+    else return hipErrorInvalidValue;
+  } else if (k == 2 && sw == 1) e = launch_nf_t<2, 1>(eps0, grid, w, n, eps2f, split_len, o, stream);
   else if (k == 4 && sw == 1) e = launch_nf_t<4, 1>(eps0, grid, w, n, eps2f, split_len, o, stream);
   else if (k == 4 && sw == 4) e = launch_nf_t<4, 4>(eps0, grid, w, n, eps2f, split_len, o, stream);
   else if (k == 4 && sw == 2) e = launch_nf_t<4, 2>(eps0, grid, w, n, eps2f, split_len, o, stream);

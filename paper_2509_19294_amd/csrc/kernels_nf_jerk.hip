@@ -41,7 +41,8 @@ template <int K, int SW, bool EPS0>
 __global__ __launch_bounds__(256) void pair_nf_jerk_kernel(const double *__restrict__ spos,
                                                            const double *__restrict__ svel,
                                                            const double *__restrict__ smass,
-                                                           const double *__restrict__ box, int64_t n,
+                                                           const double *__restrict__ box,
+                                                           const double *__restrict__ bfr, int64_t n,
                                                            float eps2f, int64_t split_len, NfjOut o) {
   constexpr int NG = 4 / SW;
   constexpr int IB = NG * 64 * K;
@@ -57,9 +58,12 @@ __global__ __launch_bounds__(256) void pair_nf_jerk_kernel(const double *__restr
   const int64_t J0 = static_cast<int64_t>(blockIdx.y) * split_len;
   const int64_t J1 = J0 + split_len < n ? J0 + split_len : n;
 
+  // a one-group block reads box, centre and threshold as the ordering pass
+  // wrote them (uniform loads, held in scalar registers)
   double bl[3], bh[3];
   {
-    const int64_t g0 = i0 / kOrderGroup, g1 = (i1 - 1) / kOrderGroup;
+    const int64_t g0 = i0 / kOrderGroup;
+    const int64_t g1 = IB == kOrderGroup ? g0 : (i1 - 1) / kOrderGroup;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       bl[c] = box[6 * g0 + c];
@@ -73,10 +77,16 @@ __global__ __launch_bounds__(256) void pair_nf_jerk_kernel(const double *__restr
       }
     }
   }
-  const double cx = 0.5 * (bl[0] + bh[0]), cy = 0.5 * (bl[1] + bh[1]), cz = 0.5 * (bl[2] + bh[2]);
+  const int64_t gb = i0 / kOrderGroup;
+  const double cx = IB == kOrderGroup ? bfr[4 * gb] : 0.5 * (bl[0] + bh[0]);
+  const double cy = IB == kOrderGroup ? bfr[4 * gb + 1] : 0.5 * (bl[1] + bh[1]);
+  const double cz = IB == kOrderGroup ? bfr[4 * gb + 2] : 0.5 * (bl[2] + bh[2]);
   const double ux = svel[3 * i0], uy = svel[3 * i0 + 1], uz = svel[3 * i0 + 2];
-  const double D2 = 0.0625 * ((bh[0] - bl[0]) * (bh[0] - bl[0]) + (bh[1] - bl[1]) * (bh[1] - bl[1]) +
-                            (bh[2] - bl[2]) * (bh[2] - bl[2]));
+  const double D2 = IB == kOrderGroup
+                        ? bfr[4 * gb + 3]
+                        : 0.0625 * ((bh[0] - bl[0]) * (bh[0] - bl[0]) +
+                                    (bh[1] - bl[1]) * (bh[1] - bl[1]) +
+                                    (bh[2] - bl[2]) * (bh[2] - bl[2]));
 
   float xh[K], yh[K], zh[K], xl[K], yl[K], zl[K], vx[K], vy[K], vz[K], mi[K];
   int64_t iidx[K];
@@ -359,10 +369,10 @@ hipError_t launch_nfj_t(bool eps0, dim3 grid, const OrderWs &w, const double *sv
                         float eps2f, int64_t split_len, const NfjOut &o, hipStream_t st) {
   if (eps0)
     pair_nf_jerk_kernel<K, SW, true>
-        <<<grid, 256, 0, st>>>(w.spos, svel, w.smass, w.box, n, eps2f, split_len, o);
+        <<<grid, 256, 0, st>>>(w.spos, svel, w.smass, w.box, w.bfr, n, eps2f, split_len, o);
   else
     pair_nf_jerk_kernel<K, SW, false>
-        <<<grid, 256, 0, st>>>(w.spos, svel, w.smass, w.box, n, eps2f, split_len, o);
+        <<<grid, 256, 0, st>>>(w.spos, svel, w.smass, w.box, w.bfr, n, eps2f, split_len, o);
   return hipGetLastError();
 }
 

@@ -2,7 +2,7 @@
 // kernel (kernels_nf.hip): a deterministic permutation that puts particles
 // close in space close in index, the positions and masses gathered in that
 // order, and a bounding box for every group of kOrderGroup consecutive
-// particles.
+// particles with its centre and a quarter of its diagonal, squared.
 //
 // Keys: each coordinate is mapped through u = asinh((x - mean) / s), with s
 // the RMS distance from the mean position per axis, so that a Plummer-like
@@ -232,9 +232,12 @@ __global__ __launch_bounds__(256) void gather_kernel(const double *__restrict__ 
 }
 
 // Bounding box of every group of kOrderGroup consecutive (ordered)
-// particles: box[6 g .. 6 g + 5] = min x, y, z, max x, y, z.
+// particles: box[6 g .. 6 g + 5] = min x, y, z, max x, y, z;
+// bfr[4 g .. 4 g + 3] = centre x, y, z and (diagonal / 4)^2, the frame and
+// far threshold of a pair-kernel block that covers exactly this group.
 __global__ __launch_bounds__(kOrderGroup) void box_kernel(const double *__restrict__ spos, int64_t n,
-                                                          double *__restrict__ box) {
+                                                          double *__restrict__ box,
+                                                          double *__restrict__ bfr) {
   __shared__ double lo[3][kOrderGroup], hi[3][kOrderGroup];
   const int t = threadIdx.x;
   const int64_t k = static_cast<int64_t>(blockIdx.x) * kOrderGroup + t;
@@ -258,6 +261,11 @@ __global__ __launch_bounds__(kOrderGroup) void box_kernel(const double *__restri
   if (t < 3) {
     box[6 * blockIdx.x + t] = lo[t][0];
     box[6 * blockIdx.x + 3 + t] = hi[t][0];
+    bfr[4 * blockIdx.x + t] = 0.5 * (lo[t][0] + hi[t][0]);
+  }
+  if (t == 0) {
+    const double ex = hi[0][0] - lo[0][0], ey = hi[1][0] - lo[1][0], ez = hi[2][0] - lo[2][0];
+    bfr[4 * blockIdx.x + 3] = 0.0625 * (ex * ex + ey * ey + ez * ez);
   }
 }
 
@@ -285,6 +293,7 @@ OrderWs order_ws_at(void *base, int64_t n) {
   const size_t o_pos = take(static_cast<size_t>(n) * 3 * sizeof(double));
   const size_t o_mass = take(static_cast<size_t>(n) * sizeof(double));
   const size_t o_box = take(static_cast<size_t>(ngroups) * 6 * sizeof(double));
+  const size_t o_bfr = take(static_cast<size_t>(ngroups) * 4 * sizeof(double));
   w.bytes = off;
   if (base) {
     char *b = static_cast<char *>(base);
@@ -298,6 +307,7 @@ OrderWs order_ws_at(void *base, int64_t n) {
     w.spos = reinterpret_cast<double *>(b + o_pos);
     w.smass = reinterpret_cast<double *>(b + o_mass);
     w.box = reinterpret_cast<double *>(b + o_box);
+    w.bfr = reinterpret_cast<double *>(b + o_bfr);
   }
   return w;
 }
@@ -332,7 +342,7 @@ hipError_t launch_order(const double *pos, const double *mass, int64_t n, const 
   // after an even number of passes the order is back in key0 / perm
   gather_kernel<<<nb, 256, 0, st>>>(pos, mass, w.perm, n, w.spos, w.smass);
   const unsigned ng = static_cast<unsigned>((n + kOrderGroup - 1) / kOrderGroup);
-  box_kernel<<<ng, kOrderGroup, 0, st>>>(w.spos, n, w.box);
+  box_kernel<<<ng, kOrderGroup, 0, st>>>(w.spos, n, w.box, w.bfr);
   return hipGetLastError();
 }
 

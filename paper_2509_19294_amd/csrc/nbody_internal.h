@@ -24,7 +24,8 @@ struct PairCfg {
   int tile;   // j-particles per tile (LDS-staged, or per wave for the scalar stream)
   int smem;   // 0: j-tiles staged in LDS; 1 (2): j streamed by scalar loads into
               // SGPRs in groups of 4 (8); 3: near/far kernel on the spatial order
-              // (compensated form only)
+              // (compensated form only); 4: near/far with the block frame stored
+              // by the ordering pass, held to 6 waves per SIMD
 };
 
 // Largest grid j-split the workspace holds for n particles.
@@ -39,8 +40,8 @@ __host__ __device__ inline int64_t padded(int64_t n) { return (n + kPad - 1) / k
 // i-particles one block covers for an item.
 inline int cfg_iblock(const PairCfg &c) { return (c.block / 64 / c.sw) * (64 / c.ls) * c.k; }
 
-// Table of compiled single-system configurations. The near/far ones (smem 3)
-// come last and exist for the compensated form only.
+// Table of compiled single-system configurations. The near/far ones (smem 3
+// and 4) come last and exist for the compensated form only.
 int single_cfg_count();
 int single_cfg_count(bool comp);
 const PairCfg &single_cfg(int idx);
@@ -116,15 +117,17 @@ struct OrderWs {
   uint32_t *hist, *scan;    // digit histograms and their scan's block totals
   double *spos, *smass;     // [n][3], [n] in the order
   double *box;              // [ceil(n / kOrderGroup)][6] min xyz, max xyz
+  double *bfr;              // [ceil(n / kOrderGroup)][4] box centre, (diagonal / 4)^2
 };
 OrderWs order_ws_at(void *base, int64_t n);
 hipError_t launch_order(const double *pos, const double *mass, int64_t n, const OrderWs &w,
                         hipStream_t stream);
 // (k targets per lane, sw waves per target group) in {(2,1), (4,1), (4,4),
-// (4,2), (2,2)}; writes acc/pot at the caller's indices.
-hipError_t launch_pair_nf(int k, int sw, const OrderWs &w, int64_t n, double eps, double G,
-                          int split, double *acc, double *pot, float4 *part, hipStream_t stream,
-                          hipEvent_t after_pair = nullptr);
+// (4,2), (2,2)}; sf (stored frame, 6 waves per SIMD) for (2,2) only; writes
+// acc/pot at the caller's indices.
+hipError_t launch_pair_nf(int k, int sw, bool sf, const OrderWs &w, int64_t n, double eps,
+                          double G, int split, double *acc, double *pot, float4 *part,
+                          hipStream_t stream, hipEvent_t after_pair = nullptr);
 
 // Acceleration + jerk (kernels_jerk.hip). Packed sources hold 2 (plain) or
 // 3 (compensated) float4 per particle, padded(n) particles; partials hold

@@ -1,4 +1,4 @@
-"""GPU parity of the near/far compensated kernel (configurations 19-23 of
+"""GPU parity of the near/far compensated kernel (configurations 19-24 of
 the compensated form): spatial ordering, per-block frames, hi-only far
 tiles. Same tolerances as the compensated form (rel-RMS <= 1e-5, worst
 particle <= 1e-4); results must be bitwise reproducible, translation must not
@@ -16,7 +16,7 @@ from paper_2509_19294_amd import ics, nbody
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-NF_CFGS = (19, 20, 21, 22, 23)
+NF_CFGS = (19, 20, 21, 22, 23, 24)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -138,7 +138,7 @@ def _shapes(n, seed):
     return {"plane": plane, "line": line, "cube": cube, "halo": halo}
 
 
-@pytest.mark.parametrize("cfg", (19, 23))
+@pytest.mark.parametrize("cfg", (19, 23, 24))
 @pytest.mark.parametrize("shape", ["plane", "line", "cube", "halo"])
 def test_degenerate_and_extreme_layouts(cfg, shape):
     """Flat, one-dimensional, uniform and huge-dynamic-range layouts: the
@@ -162,3 +162,14 @@ def test_degenerate_and_extreme_layouts(cfg, shape):
     assert orc.paper_metric(a, ra) <= 5e-4
     ds, _ = nf_accel(pos, mass, 0.01, 9, 2)  # the double-single LDS kernel
     assert orc.rel_rms(a, ra) <= 3 * orc.rel_rms(ds, ra)
+
+
+def test_stored_frame_matches_computed_frame():
+    """Configuration 24 runs configuration 23's arithmetic with the block's
+    centre and far threshold taken from the ordering pass instead of
+    recomputed: same tiles on the same paths, so the same bits."""
+    pos, _, mass = ics.plummer(20000, seed=77)
+    for split in (1, 4):
+        a23, p23 = nf_accel(pos, mass, 0.01, 23, split)
+        a24, p24 = nf_accel(pos, mass, 0.01, 24, split)
+        assert np.array_equal(a23, a24) and np.array_equal(p23, p24), split
