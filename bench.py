@@ -47,8 +47,8 @@ DEFAULT_VARIANT = {"plummer_1k": "plain", "plummer_64k": "plain", "plummer_256k"
 # whose dispatch differs reports null.
 MEASURED_TRAFFIC = {
     ("plummer_64k", "plain", 15, 16): 32541696,
-    # near/far compensated kernel, configuration 23
-    ("plummer_256k", "comp", 23, 32): 331932262,
+    # near/far compensated kernel on half box groups, configuration 25
+    ("plummer_256k", "comp", 25, 32): 339191808,
     # acceleration + jerk kernel (bench.py --hermite): shape 2, split 32
     ("plummer_64k", "plain", "jerk", 2, 32): 98617549,
 }

@@ -114,7 +114,7 @@ int size_class(int64_t n) {
 // entry and larger ones class 20's. Batched modes for classes 8..13.
 const SingleTune kTuned[2][11] = {
     {{5, 4}, {5, 8}, {5, 8}, {4, 8}, {15, 16}, {15, 16}, {15, 16}, {13, 16}, {13, 32}, {13, 8}, {15, 2}},
-    {{5, 4}, {5, 8}, {4, 4}, {0, 16}, {15, 16}, {15, 32}, {15, 32}, {23, 32}, {23, 32}, {24, 8}, {24, 8}},
+    {{5, 4}, {5, 8}, {4, 4}, {0, 16}, {15, 16}, {15, 32}, {15, 32}, {25, 32}, {25, 32}, {25, 8}, {24, 8}},
 };
 const int kTunedBatched[2][6] = {{8, 4, 4, 4, 4, 4}, {1, 4, 4, 4, 4, 4}};
 // Acceleration + jerk kernel: {shape, split} per size class 10..20, measured
@@ -302,7 +302,7 @@ hipError_t enqueue_accel(const double *pos, const double *mass, int64_t n, doubl
     if (e != hipSuccess) return e;
     hipEvent_t stop = timing_begin(st);
     const nb::PairCfg &c = nb::single_cfg(t.cfg);
-    return nb::launch_pair_nf(c.k, c.sw, c.smem == 4, w, n, eps, G, t.split, acc, pot,
+    return nb::launch_pair_nf(c.k, c.sw, c.smem - 3, w, n, eps, G, t.split, acc, pot,
                               at<float4>(ws, L.part), st, stop);
   }
   const bool smem = nb::single_cfg(t.cfg).smem != 0;

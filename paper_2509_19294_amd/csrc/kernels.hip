@@ -641,7 +641,7 @@ __global__ __launch_bounds__(256) void pair_smem_kernel(const float4 *__restrict
 // Compiled single-system configurations: {block, k, ls, sw, tile, smem}
 // (smem: 0 = LDS tiles, 1 = scalar stream with 4-source groups, 2 = with
 // 8-source groups, 3 = near/far on the spatial order, 4 = near/far with the
-// frame stored by the ordering pass).
+// frame stored by the ordering pass, 5 = near/far on half box groups).
 static const PairCfg kSingle[] = {
     {256, 1, 1, 1, 256, 0},   // 0
     {256, 2, 1, 1, 256, 0},   // 1
@@ -668,6 +668,7 @@ static const PairCfg kSingle[] = {
     {256, 4, 1, 2, 256, 3},   // 22: near/far, 512 i, two waves per target group
     {256, 2, 1, 2, 256, 3},   // 23: near/far, 256 i, two waves per target group
     {256, 2, 1, 2, 256, 4},   // 24: as 23, frame stored by the ordering pass, 6 waves per SIMD
+    {256, 2, 1, 4, 256, 5},   // 25: near/far, 128 i (half box group), four waves split the sources
 };
 int single_cfg_count() { return static_cast<int>(sizeof(kSingle) / sizeof(kSingle[0])); }
 int single_cfg_count(bool comp) { return comp ? single_cfg_count() : 19; }

@@ -4,7 +4,7 @@
 // block (four waves) takes IB = (4 / SW) * 64 * K consecutive ordered targets
 // (K per lane; SW waves share a target group and split each tile's sources,
 // their sums combined through LDS in wave order); the bounding boxes of the
-// IB / 256 groups give the block's box B, diagonal D, and the centre of B is
+// IB / 256 groups (of its half group, for IB = 128) give the block's box B, diagonal D, and the centre of B is
 // its FP64 frame c. Source tiles of 256 ordered particles are staged in
 // LDS relative to c, and each tile takes one of two paths, the same for the
 // whole block:
@@ -44,27 +44,32 @@ constexpr int nf_lds_float4() {
   return tiles > combine ? tiles : combine;
 }
 
-// SF: the block covers one box group and reads its box, centre and
-// threshold as the ordering pass wrote them (uniform loads, which stay in
-// scalar registers), and the compiler is held to 6 waves per SIMD, which the
-// two-target shape then reaches without spills (94 -> 74 VGPRs). Otherwise
-// the block computes them and the compiler picks the occupancy.
-template <bool SF>
+// Frame modes. FR 0: the block covers whole box groups and computes the
+// union of their boxes, its centre and threshold. FR 1: the block covers one
+// box group and reads its box, centre and threshold as the ordering pass
+// wrote them (uniform loads, which stay in scalar registers), and the
+// compiler is held to 6 waves per SIMD, which the two-target shape then
+// reaches without spills (94 -> 74 VGPRs). FR 2: the block covers half a box
+// group (128 targets) and reads that half's box, centre and threshold: a
+// smaller target box makes more source tiles far; the compiler is held to 6
+// waves per SIMD as for FR 1.
+template <int FR>
 constexpr int nf_waves() {
-  return SF ? 6 : 1;
+  return FR != 0 ? 6 : 1;
 }
 
-template <int K, int SW, bool SF, bool EPS0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(nf_waves<SF>()))) void
-pair_nf_kernel(const double *__restrict__ spos,
-                                                      const double *__restrict__ smass,
-                                                      const double *__restrict__ box,
-                                                      const double *__restrict__ bfr, int64_t n,
-                                                      float eps2f, int64_t split_len, NfOut o) {
+template <int K, int SW, int FR, bool EPS0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(nf_waves<FR>()))) void
+pair_nf_kernel(const double *__restrict__ spos, const double *__restrict__ smass,
+               const double *__restrict__ box, const double *__restrict__ bfr,
+               const double *__restrict__ hbox, int64_t n, float eps2f, int64_t split_len,
+               NfOut o) {
   constexpr int NG = 4 / SW;          // target groups of 64 lanes per block
   constexpr int IB = NG * 64 * K;
-  static_assert(IB % kOrderGroup == 0 && 4 % SW == 0, "block shape");
-  static_assert(!SF || IB == kOrderGroup, "stored frame: one box group per block");
+  constexpr int kHalf = kNfTile / 2;
+  static_assert(4 % SW == 0, "block shape");
+  static_assert(FR == 0 ? IB % kOrderGroup == 0 : IB == (FR == 1 ? kOrderGroup : kHalf),
+                "frame mode and block shape");
   __shared__ float4 smem[nf_lds_float4<K, SW>()];
   float4 (*lds)[2 * kNfTile] = reinterpret_cast<float4 (*)[2 * kNfTile]>(smem);
   const int tid = threadIdx.x;
@@ -76,11 +81,23 @@ pair_nf_kernel(const double *__restrict__ spos,
   const int64_t J0 = static_cast<int64_t>(blockIdx.y) * split_len;
   const int64_t J1 = J0 + split_len < n ? J0 + split_len : n;
 
-  // the block's box: union of its groups' boxes; the frame is its centre
-  double bl[3], bh[3];
-  {
+  // the block's box: union of its groups' boxes (or its half group's box);
+  // the frame is its centre
+  double bl[3], bh[3], cx, cy, cz, D2;  // D2: far threshold (D / 4)^2
+  if constexpr (FR == 2) {
+    const int64_t h = i0 / kHalf;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      bl[c] = hbox[10 * h + c];
+      bh[c] = hbox[10 * h + 3 + c];
+    }
+    cx = hbox[10 * h + 6];
+    cy = hbox[10 * h + 7];
+    cz = hbox[10 * h + 8];
+    D2 = hbox[10 * h + 9];
+  } else {
     const int64_t g0 = i0 / kOrderGroup;
-    const int64_t g1 = SF ? g0 : (i1 - 1) / kOrderGroup;
+    const int64_t g1 = FR == 1 ? g0 : (i1 - 1) / kOrderGroup;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       bl[c] = box[6 * g0 + c];
@@ -93,16 +110,19 @@ pair_nf_kernel(const double *__restrict__ spos,
         bh[c] = fmax(bh[c], box[6 * g + 3 + c]);
       }
     }
+    if constexpr (FR == 1) {
+      cx = bfr[4 * g0];
+      cy = bfr[4 * g0 + 1];
+      cz = bfr[4 * g0 + 2];
+      D2 = bfr[4 * g0 + 3];
+    } else {
+      cx = 0.5 * (bl[0] + bh[0]);
+      cy = 0.5 * (bl[1] + bh[1]);
+      cz = 0.5 * (bl[2] + bh[2]);
+      D2 = 0.0625 * ((bh[0] - bl[0]) * (bh[0] - bl[0]) + (bh[1] - bl[1]) * (bh[1] - bl[1]) +
+                     (bh[2] - bl[2]) * (bh[2] - bl[2]));
+    }
   }
-  const int64_t gb = i0 / kOrderGroup;
-  const double cx = SF ? bfr[4 * gb] : 0.5 * (bl[0] + bh[0]);
-  const double cy = SF ? bfr[4 * gb + 1] : 0.5 * (bl[1] + bh[1]);
-  const double cz = SF ? bfr[4 * gb + 2] : 0.5 * (bl[2] + bh[2]);
-  // far threshold: (D / 4)^2
-  const double D2 = SF ? bfr[4 * gb + 3]
-                       : 0.0625 * ((bh[0] - bl[0]) * (bh[0] - bl[0]) +
-                                   (bh[1] - bl[1]) * (bh[1] - bl[1]) +
-                                   (bh[2] - bl[2]) * (bh[2] - bl[2]));
 
   float xh[K], yh[K], zh[K], xl[K], yl[K], zl[K], mi[K];
   int64_t iidx[K];
@@ -336,21 +356,21 @@ __global__ __launch_bounds__(256) void combine_nf_kernel(const float4 *__restric
   }
 }
 
-template <int K, int SW, bool SF = false>
+template <int K, int SW, int FR = 0>
 hipError_t launch_nf_t(bool eps0, dim3 grid, const OrderWs &w, int64_t n, float eps2f,
                        int64_t split_len, const NfOut &o, hipStream_t st) {
   if (eps0)
-    pair_nf_kernel<K, SW, SF, true>
-        <<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, w.bfr, n, eps2f, split_len, o);
+    pair_nf_kernel<K, SW, FR, true>
+        <<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, w.bfr, w.hbox, n, eps2f, split_len, o);
   else
-    pair_nf_kernel<K, SW, SF, false>
-        <<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, w.bfr, n, eps2f, split_len, o);
+    pair_nf_kernel<K, SW, FR, false>
+        <<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, w.bfr, w.hbox, n, eps2f, split_len, o);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_pair_nf(int k, int sw, bool sf, const OrderWs &w, int64_t n, double eps,
+hipError_t launch_pair_nf(int k, int sw, int fr, const OrderWs &w, int64_t n, double eps,
                           double G, int split, double *acc, double *pot, float4 *part,
                           hipStream_t stream, hipEvent_t after_pair) {
   if (n <= 0) return hipSuccess;
@@ -374,10 +394,12 @@ hipError_t launch_pair_nf(int k, int sw, bool sf, const OrderWs &w, int64_t n, d
   }
   dim3 grid(static_cast<unsigned>(nblk), static_cast<unsigned>(split));
   hipError_t e;
-  if (sf) {
-    if (k == 2 && sw == 2) e = launch_nf_t<2, 2, true>(eps0, grid, w, n, eps2f, split_len, o, stream);
-    else return hipErrorInvalidValue;
-  } else if (k == 2 && sw == 1) e = launch_nf_t<2, 1>(eps0, grid, w, n, eps2f, split_len, o, stream);
+  if (fr == 1 && k == 2 && sw == 2)
+    e = launch_nf_t<2, 2, 1>(eps0, grid, w, n, eps2f, split_len, o, stream);
+  else if (fr == 2 && k == 2 && sw == 4)
+    e = launch_nf_t<2, 4, 2>(eps0, grid, w, n, eps2f, split_len, o, stream);
+  else if (fr != 0) return hipErrorInvalidValue;
+  else if (k == 2 && sw == 1) e = launch_nf_t<2, 1>(eps0, grid, w, n, eps2f, split_len, o, stream);
   else if (k == 4 && sw == 1) e = launch_nf_t<4, 1>(eps0, grid, w, n, eps2f, split_len, o, stream);
   else if (k == 4 && sw == 4) e = launch_nf_t<4, 4>(eps0, grid, w, n, eps2f, split_len, o, stream);
   else if (k == 4 && sw == 2) e = launch_nf_t<4, 2>(eps0, grid, w, n, eps2f, split_len, o, stream);

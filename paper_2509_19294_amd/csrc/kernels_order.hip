@@ -2,7 +2,8 @@
 // kernel (kernels_nf.hip): a deterministic permutation that puts particles
 // close in space close in index, the positions and masses gathered in that
 // order, and a bounding box for every group of kOrderGroup consecutive
-// particles with its centre and a quarter of its diagonal, squared.
+// particles and every half group, with their centres and a quarter of their
+// diagonals, squared.
 //
 // Keys: each coordinate is mapped through u = asinh((x - mean) / s), with s
 // the RMS distance from the mean position per axis, so that a Plummer-like
@@ -234,10 +235,15 @@ __global__ __launch_bounds__(256) void gather_kernel(const double *__restrict__ 
 // Bounding box of every group of kOrderGroup consecutive (ordered)
 // particles: box[6 g .. 6 g + 5] = min x, y, z, max x, y, z;
 // bfr[4 g .. 4 g + 3] = centre x, y, z and (diagonal / 4)^2, the frame and
-// far threshold of a pair-kernel block that covers exactly this group.
+// far threshold of a pair-kernel block that covers exactly this group; and
+// the same for each half group h = 2 g, 2 g + 1: hbox[10 h .. 10 h + 9] =
+// min xyz, max xyz, centre xyz, (diagonal / 4)^2. A half group past the end
+// holds min +inf and max -inf (every box is then at infinite distance).
 __global__ __launch_bounds__(kOrderGroup) void box_kernel(const double *__restrict__ spos, int64_t n,
                                                           double *__restrict__ box,
-                                                          double *__restrict__ bfr) {
+                                                          double *__restrict__ bfr,
+                                                          double *__restrict__ hbox) {
+  constexpr int kHalf = kOrderGroup / 2;
   __shared__ double lo[3][kOrderGroup], hi[3][kOrderGroup];
   const int t = threadIdx.x;
   const int64_t k = static_cast<int64_t>(blockIdx.x) * kOrderGroup + t;
@@ -248,8 +254,9 @@ __global__ __launch_bounds__(kOrderGroup) void box_kernel(const double *__restri
     hi[c][t] = k < n ? x : -HUGE_VAL;
   }
   __syncthreads();
-  for (int w = kOrderGroup / 2; w > 0; w >>= 1) {
-    if (t < w) {
+  // each half reduced on its own: lo[.][0] and lo[.][kHalf] hold the halves
+  for (int w = kHalf / 2; w > 0; w >>= 1) {
+    if ((t & (kHalf - 1)) < w) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         lo[c][t] = fmin(lo[c][t], lo[c][t + w]);
@@ -258,13 +265,31 @@ __global__ __launch_bounds__(kOrderGroup) void box_kernel(const double *__restri
     }
     __syncthreads();
   }
+  if (t < 2) {
+    const int64_t h = 2 * static_cast<int64_t>(blockIdx.x) + t;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double l = lo[c][t * kHalf], u = hi[c][t * kHalf];
+      hbox[10 * h + c] = l;
+      hbox[10 * h + 3 + c] = u;
+      hbox[10 * h + 6 + c] = 0.5 * (l + u);
+    }
+    const double ex = hi[0][t * kHalf] - lo[0][t * kHalf];
+    const double ey = hi[1][t * kHalf] - lo[1][t * kHalf];
+    const double ez = hi[2][t * kHalf] - lo[2][t * kHalf];
+    hbox[10 * h + 9] = 0.0625 * (ex * ex + ey * ey + ez * ez);
+  }
   if (t < 3) {
-    box[6 * blockIdx.x + t] = lo[t][0];
-    box[6 * blockIdx.x + 3 + t] = hi[t][0];
-    bfr[4 * blockIdx.x + t] = 0.5 * (lo[t][0] + hi[t][0]);
+    const double l = fmin(lo[t][0], lo[t][kHalf]), u = fmax(hi[t][0], hi[t][kHalf]);
+    box[6 * blockIdx.x + t] = l;
+    box[6 * blockIdx.x + 3 + t] = u;
+    bfr[4 * blockIdx.x + t] = 0.5 * (l + u);
   }
   if (t == 0) {
-    const double ex = hi[0][0] - lo[0][0], ey = hi[1][0] - lo[1][0], ez = hi[2][0] - lo[2][0];
+    // the same expression as the pair kernel's own threshold of a group
+    const double ex = fmax(hi[0][0], hi[0][kHalf]) - fmin(lo[0][0], lo[0][kHalf]);
+    const double ey = fmax(hi[1][0], hi[1][kHalf]) - fmin(lo[1][0], lo[1][kHalf]);
+    const double ez = fmax(hi[2][0], hi[2][kHalf]) - fmin(lo[2][0], lo[2][kHalf]);
     bfr[4 * blockIdx.x + 3] = 0.0625 * (ex * ex + ey * ey + ez * ez);
   }
 }
@@ -294,6 +319,7 @@ OrderWs order_ws_at(void *base, int64_t n) {
   const size_t o_mass = take(static_cast<size_t>(n) * sizeof(double));
   const size_t o_box = take(static_cast<size_t>(ngroups) * 6 * sizeof(double));
   const size_t o_bfr = take(static_cast<size_t>(ngroups) * 4 * sizeof(double));
+  const size_t o_hbox = take(static_cast<size_t>(ngroups) * 2 * 10 * sizeof(double));
   w.bytes = off;
   if (base) {
     char *b = static_cast<char *>(base);
@@ -308,6 +334,7 @@ OrderWs order_ws_at(void *base, int64_t n) {
     w.smass = reinterpret_cast<double *>(b + o_mass);
     w.box = reinterpret_cast<double *>(b + o_box);
     w.bfr = reinterpret_cast<double *>(b + o_bfr);
+    w.hbox = reinterpret_cast<double *>(b + o_hbox);
   }
   return w;
 }
@@ -342,7 +369,7 @@ hipError_t launch_order(const double *pos, const double *mass, int64_t n, const 
   // after an even number of passes the order is back in key0 / perm
   gather_kernel<<<nb, 256, 0, st>>>(pos, mass, w.perm, n, w.spos, w.smass);
   const unsigned ng = static_cast<unsigned>((n + kOrderGroup - 1) / kOrderGroup);
-  box_kernel<<<ng, kOrderGroup, 0, st>>>(w.spos, n, w.box, w.bfr);
+  box_kernel<<<ng, kOrderGroup, 0, st>>>(w.spos, n, w.box, w.bfr, w.hbox);
   return hipGetLastError();
 }
 

@@ -25,7 +25,8 @@ struct PairCfg {
   int smem;   // 0: j-tiles staged in LDS; 1 (2): j streamed by scalar loads into
               // SGPRs in groups of 4 (8); 3: near/far kernel on the spatial order
               // (compensated form only); 4: near/far with the block frame stored
-              // by the ordering pass, held to 6 waves per SIMD
+              // by the ordering pass, held to 6 waves per SIMD; 5: near/far on
+              // half box groups (128 targets per block), likewise
 };
 
 // Largest grid j-split the workspace holds for n particles.
@@ -118,14 +119,16 @@ struct OrderWs {
   double *spos, *smass;     // [n][3], [n] in the order
   double *box;              // [ceil(n / kOrderGroup)][6] min xyz, max xyz
   double *bfr;              // [ceil(n / kOrderGroup)][4] box centre, (diagonal / 4)^2
+  double *hbox;             // [2 ceil(n / kOrderGroup)][10] half groups: min, max, centre, (D / 4)^2
 };
 OrderWs order_ws_at(void *base, int64_t n);
 hipError_t launch_order(const double *pos, const double *mass, int64_t n, const OrderWs &w,
                         hipStream_t stream);
 // (k targets per lane, sw waves per target group) in {(2,1), (4,1), (4,4),
-// (4,2), (2,2)}; sf (stored frame, 6 waves per SIMD) for (2,2) only; writes
-// acc/pot at the caller's indices.
-hipError_t launch_pair_nf(int k, int sw, bool sf, const OrderWs &w, int64_t n, double eps,
+// (4,2), (2,2)} with the frame computed (fr 0); fr 1 (stored frame of a box
+// group, 6 waves per SIMD) for (2,2), fr 2 (stored frame of a half group,
+// 6 waves per SIMD) for (2,4). Writes acc/pot at the caller's indices.
+hipError_t launch_pair_nf(int k, int sw, int fr, const OrderWs &w, int64_t n, double eps,
                           double G, int split, double *acc, double *pot, float4 *part,
                           hipStream_t stream, hipEvent_t after_pair = nullptr);
 

@@ -1,4 +1,4 @@
-"""GPU parity of the near/far compensated kernel (configurations 19-24 of
+"""GPU parity of the near/far compensated kernel (configurations 19-25 of
 the compensated form): spatial ordering, per-block frames, hi-only far
 tiles. Same tolerances as the compensated form (rel-RMS <= 1e-5, worst
 particle <= 1e-4); results must be bitwise reproducible, translation must not
@@ -16,7 +16,7 @@ from paper_2509_19294_amd import ics, nbody
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-NF_CFGS = (19, 20, 21, 22, 23, 24)
+NF_CFGS = (19, 20, 21, 22, 23, 24, 25)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -138,7 +138,7 @@ def _shapes(n, seed):
     return {"plane": plane, "line": line, "cube": cube, "halo": halo}
 
 
-@pytest.mark.parametrize("cfg", (19, 23, 24))
+@pytest.mark.parametrize("cfg", (19, 23, 24, 25))
 @pytest.mark.parametrize("shape", ["plane", "line", "cube", "halo"])
 def test_degenerate_and_extreme_layouts(cfg, shape):
     """Flat, one-dimensional, uniform and huge-dynamic-range layouts: the
