@@ -122,7 +122,7 @@ const int kTunedBatched[2][6] = {{8, 4, 4, 4, 4, 4}, {1, 4, 4, 4, 4, 4}};
 // eps = 0.01; split 0 would select the rule of jerk_default_split).
 const SingleTune kTunedJerk[2][11] = {
     {{8, 1}, {8, 2}, {8, 4}, {2, 8}, {2, 16}, {2, 32}, {2, 32}, {2, 32}, {1, 32}, {0, 16}, {2, 2}},
-    {{2, 1}, {2, 2}, {2, 4}, {2, 8}, {2, 16}, {10, 32}, {10, 32}, {10, 32}, {10, 32}, {10, 16}, {10, 8}},
+    {{2, 1}, {2, 2}, {2, 4}, {2, 8}, {2, 16}, {12, 32}, {12, 32}, {12, 32}, {12, 32}, {12, 16}, {10, 8}},
 };
 SingleTune g_jerk[2][kClasses];
 int g_jerk_forced[2] = {-1, -1};

@@ -445,8 +445,9 @@ struct JerkShape {
   int k, sw;
 };
 constexpr JerkShape kJerkShapes[] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2}, {2, 4},
-                                     {4, 1}, {4, 2}, {1, 4}, {1, 2}, {1, 1}, {2, 2}};
-// shapes 10 and 11: near/far kernel on the spatial order (compensated form)
+                                     {4, 1}, {4, 2}, {1, 4}, {1, 2}, {1, 1}, {2, 2}, {1, 2}};
+// shapes 10-12: near/far kernel on the spatial order (compensated form);
+// shape 12 takes half a box group (128 targets) per block
 constexpr int kJerkFirstNf = 10;
 constexpr int kJerkShapeCount = static_cast<int>(sizeof(kJerkShapes) / sizeof(kJerkShapes[0]));
 

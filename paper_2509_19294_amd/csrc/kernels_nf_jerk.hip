@@ -2,9 +2,10 @@
 // scheme of kernels_nf.hip applied to the jerk pair sum of kernels_jerk.hip.
 //
 // On the spatial order (kernels_order.hip, velocities gathered beside the
-// positions), a block of IB = (4 / SW) * 64 * K ordered targets takes the
-// centre of its box (diagonal D) as its FP64 position frame c and the
-// velocity of its first target as its velocity frame u. Each 256-source tile
+// positions), a block of IB = (4 / SW) * 64 * K ordered targets (whole box
+// groups, or half of one) takes the centre of its box (diagonal D) as its
+// FP64 position frame c and the velocity of its first target as its
+// velocity frame u. Each 256-source tile
 // is staged in LDS as {hi(x - c), m}, {lo(x - c), 0}, {fp32(v - u), 0};
 // source tiles at least D / 4 from the block's box skip the lo parts (the
 // separation then carries at most 6 u |d| of error, see kernels_nf.hip).
@@ -37,16 +38,21 @@ constexpr int nfj_lds_float4() {
   return tiles > combine ? tiles : combine;
 }
 
-template <int K, int SW, bool EPS0>
+// HG: the block covers half a box group (128 targets) and reads that half's
+// box, centre and threshold from the ordering pass; a smaller target box
+// makes more source tiles far.
+template <int K, int SW, bool HG, bool EPS0>
 __global__ __launch_bounds__(256) void pair_nf_jerk_kernel(const double *__restrict__ spos,
                                                            const double *__restrict__ svel,
                                                            const double *__restrict__ smass,
                                                            const double *__restrict__ box,
-                                                           const double *__restrict__ bfr, int64_t n,
+                                                           const double *__restrict__ bfr,
+                                                           const double *__restrict__ hbox, int64_t n,
                                                            float eps2f, int64_t split_len, NfjOut o) {
   constexpr int NG = 4 / SW;
   constexpr int IB = NG * 64 * K;
-  static_assert(IB % kOrderGroup == 0 && 4 % SW == 0, "block shape");
+  static_assert(4 % SW == 0 && (HG ? IB == kOrderGroup / 2 : IB % kOrderGroup == 0),
+                "block shape");
   __shared__ float4 smem[nfj_lds_float4<K, SW>()];
   float4 (*lds)[3 * kNfjTile] = reinterpret_cast<float4 (*)[3 * kNfjTile]>(smem);
   const int tid = threadIdx.x;
@@ -58,10 +64,21 @@ __global__ __launch_bounds__(256) void pair_nf_jerk_kernel(const double *__restr
   const int64_t J0 = static_cast<int64_t>(blockIdx.y) * split_len;
   const int64_t J1 = J0 + split_len < n ? J0 + split_len : n;
 
-  // a one-group block reads box, centre and threshold as the ordering pass
-  // wrote them (uniform loads, held in scalar registers)
-  double bl[3], bh[3];
-  {
+  // a one-group (half-group) block reads box, centre and threshold as the
+  // ordering pass wrote them (uniform loads, held in scalar registers)
+  double bl[3], bh[3], cx, cy, cz, D2;
+  if constexpr (HG) {
+    const int64_t h = i0 / (kOrderGroup / 2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      bl[c] = hbox[10 * h + c];
+      bh[c] = hbox[10 * h + 3 + c];
+    }
+    cx = hbox[10 * h + 6];
+    cy = hbox[10 * h + 7];
+    cz = hbox[10 * h + 8];
+    D2 = hbox[10 * h + 9];
+  } else {
     const int64_t g0 = i0 / kOrderGroup;
     const int64_t g1 = IB == kOrderGroup ? g0 : (i1 - 1) / kOrderGroup;
 #pragma unroll
@@ -76,17 +93,15 @@ __global__ __launch_bounds__(256) void pair_nf_jerk_kernel(const double *__restr
         bh[c] = fmax(bh[c], box[6 * g + 3 + c]);
       }
     }
+    cx = IB == kOrderGroup ? bfr[4 * g0] : 0.5 * (bl[0] + bh[0]);
+    cy = IB == kOrderGroup ? bfr[4 * g0 + 1] : 0.5 * (bl[1] + bh[1]);
+    cz = IB == kOrderGroup ? bfr[4 * g0 + 2] : 0.5 * (bl[2] + bh[2]);
+    D2 = IB == kOrderGroup ? bfr[4 * g0 + 3]
+                           : 0.0625 * ((bh[0] - bl[0]) * (bh[0] - bl[0]) +
+                                       (bh[1] - bl[1]) * (bh[1] - bl[1]) +
+                                       (bh[2] - bl[2]) * (bh[2] - bl[2]));
   }
-  const int64_t gb = i0 / kOrderGroup;
-  const double cx = IB == kOrderGroup ? bfr[4 * gb] : 0.5 * (bl[0] + bh[0]);
-  const double cy = IB == kOrderGroup ? bfr[4 * gb + 1] : 0.5 * (bl[1] + bh[1]);
-  const double cz = IB == kOrderGroup ? bfr[4 * gb + 2] : 0.5 * (bl[2] + bh[2]);
   const double ux = svel[3 * i0], uy = svel[3 * i0 + 1], uz = svel[3 * i0 + 2];
-  const double D2 = IB == kOrderGroup
-                        ? bfr[4 * gb + 3]
-                        : 0.0625 * ((bh[0] - bl[0]) * (bh[0] - bl[0]) +
-                                    (bh[1] - bl[1]) * (bh[1] - bl[1]) +
-                                    (bh[2] - bl[2]) * (bh[2] - bl[2]));
 
   float xh[K], yh[K], zh[K], xl[K], yl[K], zl[K], vx[K], vy[K], vz[K], mi[K];
   int64_t iidx[K];
@@ -364,15 +379,15 @@ __global__ __launch_bounds__(256) void gather_vel_kernel(const double *__restric
   svel[3 * k + 2] = vel[3 * j + 2];
 }
 
-template <int K, int SW>
+template <int K, int SW, bool HG = false>
 hipError_t launch_nfj_t(bool eps0, dim3 grid, const OrderWs &w, const double *svel, int64_t n,
                         float eps2f, int64_t split_len, const NfjOut &o, hipStream_t st) {
   if (eps0)
-    pair_nf_jerk_kernel<K, SW, true>
-        <<<grid, 256, 0, st>>>(w.spos, svel, w.smass, w.box, w.bfr, n, eps2f, split_len, o);
+    pair_nf_jerk_kernel<K, SW, HG, true><<<grid, 256, 0, st>>>(
+        w.spos, svel, w.smass, w.box, w.bfr, w.hbox, n, eps2f, split_len, o);
   else
-    pair_nf_jerk_kernel<K, SW, false>
-        <<<grid, 256, 0, st>>>(w.spos, svel, w.smass, w.box, w.bfr, n, eps2f, split_len, o);
+    pair_nf_jerk_kernel<K, SW, HG, false><<<grid, 256, 0, st>>>(
+        w.spos, svel, w.smass, w.box, w.bfr, w.hbox, n, eps2f, split_len, o);
   return hipGetLastError();
 }
 
@@ -413,6 +428,8 @@ hipError_t launch_pair_nf_jerk(int k, int sw, const OrderWs &w, const double *sv
   hipError_t e;
   if (k == 1 && sw == 1) e = launch_nfj_t<1, 1>(eps0, grid, w, svel, n, eps2f, split_len, o, stream);
   else if (k == 2 && sw == 2) e = launch_nfj_t<2, 2>(eps0, grid, w, svel, n, eps2f, split_len, o, stream);
+  else if (k == 1 && sw == 2)
+    e = launch_nfj_t<1, 2, true>(eps0, grid, w, svel, n, eps2f, split_len, o, stream);
   else return hipErrorInvalidValue;
   if (e == hipSuccess && after_pair) e = hipEventRecord(after_pair, stream);
   if (e != hipSuccess || split == 1) return e;

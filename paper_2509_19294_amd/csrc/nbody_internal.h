@@ -138,7 +138,8 @@ hipError_t launch_pair_nf(int k, int sw, int fr, const OrderWs &w, int64_t n, do
 // Compiled kernel shapes: cfg in [0, jerk_shape_count(comp)); K targets per
 // lane and SW waves splitting the sources of a target group. The near/far
 // shapes (jerk_shape_nf) exist for the compensated form only and run on the
-// spatial order (launch_order, launch_gather_vel, launch_pair_nf_jerk).
+// spatial order (launch_order, launch_gather_vel, launch_pair_nf_jerk with
+// (k, sw) = (1, 1) or (2, 2) on whole box groups, (1, 2) on half groups).
 int jerk_shape_count();
 int jerk_shape_count(bool comp);
 bool jerk_shape_nf(int cfg);

@@ -225,7 +225,7 @@ def test_jerk_entry_points_validate(lib):
 def test_jerk_shapes_and_forcing(lib, tmp_path):
     shapes = nbody.jerk_shapes()
     assert len(shapes) == lib.nbody_tune_jerk_count(0) >= 4
-    assert lib.nbody_tune_jerk_count(1) == len(shapes) + 2 and lib.nbody_tune_jerk_count(9) == 0
+    assert lib.nbody_tune_jerk_count(1) == len(shapes) + 3 and lib.nbody_tune_jerk_count(9) == 0
     assert lib.nbody_tune_jerk_set(0, 10) == nbody.EINVAL   # near/far shapes: compensated only
     assert lib.nbody_tune_jerk_set(1, 10) == nbody.OK
     assert lib.nbody_tune_jerk_set(1, -1) == nbody.OK

@@ -121,7 +121,7 @@ def test_every_shape_and_split(variant, eps):
         nbody.tune_jerk_set(variant, -1)
 
 
-@pytest.mark.parametrize("cfg", [10, 11])
+@pytest.mark.parametrize("cfg", [10, 11, 12])
 def test_near_far_shapes(cfg):
     """Near/far shapes (compensated form): tiny and ragged sizes, eps 0,
     a translated and boosted system, a permuted input, bitwise
