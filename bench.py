@@ -49,8 +49,12 @@ MEASURED_TRAFFIC = {
     ("plummer_64k", "plain", 15, 16): 32541696,
     # near/far compensated kernel on half box groups, configuration 25
     ("plummer_256k", "comp", 25, 32): 339191808,
+    # near/far with the stored frame, configuration 24
+    ("kroupa_1m", "comp", 24, 8): 8304729638,
     # acceleration + jerk kernel (bench.py --hermite): shape 2, split 32
     ("plummer_64k", "plain", "jerk", 2, 32): 98617549,
+    # near/far acceleration + jerk kernel on half box groups, shape 12
+    ("plummer_256k", "comp", "jerk", 12, 32): 1024842773,
 }
 
 
