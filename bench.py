@@ -48,13 +48,13 @@ DEFAULT_VARIANT = {"plummer_1k": "plain", "plummer_64k": "plain", "plummer_256k"
 MEASURED_TRAFFIC = {
     ("plummer_64k", "plain", 15, 16): 32541696,
     # near/far compensated kernel on half box groups, configuration 25
-    ("plummer_256k", "comp", 25, 32): 339191808,
+    ("plummer_256k", "comp", 25, 32): 334628974,
     # near/far with the stored frame, configuration 24
-    ("kroupa_1m", "comp", 24, 8): 8304729638,
+    ("kroupa_1m", "comp", 24, 8): 7920856990,
     # acceleration + jerk kernel (bench.py --hermite): shape 2, split 32
     ("plummer_64k", "plain", "jerk", 2, 32): 98617549,
     # near/far acceleration + jerk kernel on half box groups, shape 12
-    ("plummer_256k", "comp", "jerk", 12, 32): 1024842773,
+    ("plummer_256k", "comp", "jerk", 12, 32): 687650464,
 }
 
 

@@ -15,6 +15,14 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
   e = (a - (s - bb)) + (b - bb);
 }
 
+// Streaming store of a partial sum that only a later kernel reads: marked
+// non-temporal, so it does not push reusable data out of the L2.
+__device__ __forceinline__ void store_stream(float4 *p, float4 v) {
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  const f32x4 w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, reinterpret_cast<f32x4 *>(p));
+}
+
 // Double-single split of an FP64 offset: hi = fp32(d), lo = fp32(d - hi).
 __device__ __forceinline__ void ds_split(double d, float &hi, float &lo) {
   hi = static_cast<float>(d);

@@ -309,8 +309,8 @@ pair_nf_kernel(const double *__restrict__ spos, const double *__restrict__ smass
     if (i >= i1) continue;
     if (o.part) {
       float4 *P = o.part + (static_cast<int64_t>(blockIdx.y) * o.n + i) * 2;
-      P[0] = make_float4(ah[k][0], ah[k][1], ah[k][2], ah[k][3]);
-      P[1] = make_float4(al[k][0], al[k][1], al[k][2], al[k][3]);
+      store_stream(P, make_float4(ah[k][0], ah[k][1], ah[k][2], ah[k][3]));
+      store_stream(P + 1, make_float4(al[k][0], al[k][1], al[k][2], al[k][3]));
     } else {
       double s[4];
 #pragma unroll

@@ -310,10 +310,10 @@ __global__ __launch_bounds__(256) void pair_nf_jerk_kernel(const double *__restr
         jl[c] = fmaf(-3.0f, al[k][7 + c], al[k][4 + c]) + (pe + he);
       }
       float4 *P = o.part + (static_cast<int64_t>(blockIdx.y) * o.n + i) * 4;
-      P[0] = make_float4(ah[k][0], ah[k][1], ah[k][2], ah[k][3]);
-      P[1] = make_float4(jh[0], jh[1], jh[2], 0.f);
-      P[2] = make_float4(al[k][0], al[k][1], al[k][2], al[k][3]);
-      P[3] = make_float4(jl[0], jl[1], jl[2], 0.f);
+      store_stream(P, make_float4(ah[k][0], ah[k][1], ah[k][2], ah[k][3]));
+      store_stream(P + 1, make_float4(jh[0], jh[1], jh[2], 0.f));
+      store_stream(P + 2, make_float4(al[k][0], al[k][1], al[k][2], al[k][3]));
+      store_stream(P + 3, make_float4(jl[0], jl[1], jl[2], 0.f));
     } else {
       double s[kNQ];
 #pragma unroll
