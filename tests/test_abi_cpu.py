@@ -160,6 +160,15 @@ def test_tuning_table(lib, tmp_path):
         assert ib == (block // 64 // sw) * (64 // ls) * k
     modes = nbody.batched_modes()
     assert len(modes) >= 2
+    # the near/far configurations exist for the compensated form only; the
+    # half-group one covers 128 targets per block, the others whole groups
+    comp = nbody.tune_configs("comp")
+    assert len(comp) == len(cfgs) + 7
+    for c in range(len(cfgs), len(comp)):
+        assert comp[c][5] % 256 == 0 or c == len(comp) - 1
+        with pytest.raises(nbody.NbodyError):
+            nbody.tune_set("plain", 18, c, 1)
+    assert comp[-1] == (256, 2, 1, 4, 256, 128)
     buf = (ctypes.c_int32 * 6)()
     assert lib.nbody_tune_describe(0, 999, buf) == nbody.EINVAL
     assert lib.nbody_tune_describe(5, 0, buf) == nbody.ENOTSUP
