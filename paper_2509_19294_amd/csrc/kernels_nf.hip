@@ -4,10 +4,10 @@
 // block (four waves) takes IB = (4 / SW) * 64 * K consecutive ordered targets
 // (K per lane; SW waves share a target group and split each tile's sources,
 // their sums combined through LDS in wave order); the bounding boxes of the
-// IB / 256 groups (of its half group, for IB = 128) give the block's box B, diagonal D, and the centre of B is
-// its FP64 frame c. Source tiles of 256 ordered particles are staged in
-// LDS relative to c, and each tile takes one of two paths, the same for the
-// whole block:
+// IB / 256 groups (or of its half group, for IB = 128) give the block's box
+// B, diagonal D, and the centre of B is its FP64 frame c. Source tiles of
+// 256 ordered particles are staged in LDS relative to c, and each tile takes
+// one of two paths, the same for the whole block:
 //   * near (the tile's box lies closer to B than D / 4): double-single
 //     staging, separation (hi_j - hi_i) + (lo_j - lo_i), as in the
 //     compensated form;
