@@ -3,6 +3,12 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--variant plain|comp] [--hermite] [--full-run] [--paper-run]
 
+The default workload is the largest single-GPU system: a Plummer sphere of
+N = 1,048,576 particles with Kroupa masses (seed 3), eps = 0.001,
+dt = 1/1024, in the compensated form (double-single coordinates on a spatial
+order, far tiles on the hi words); the plain FP32 kernel is timed beside it
+on the same inputs.
+
 A step is one kick-drift-kick leapfrog step of the whole path: kick and drift
 (FP64), the force evaluation (pack or double-single staging, the FP32 pair
 kernel, the j-split combine, the FP64 epilogue) and the closing kick fused
@@ -63,7 +69,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plummer_64k",
+    ap.add_argument("--workload", default="kroupa_1m",
                     choices=sorted(DEFAULT_VARIANT))
     ap.add_argument("--variant", default=None, choices=["plain", "comp"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -96,10 +102,12 @@ def full_run(name, variant, steps=None):
     nbody.load()
     dev = torch.device("cuda:0")
     plan = None
+    te = None
     if name == "ensemble_512":
         ens, spec = ics.workload(name)
         pos, vel, mass, eps = ens.pos, ens.vel, ens.mass, 0.0
-        plan = nbody.Plan(ens.offsets, ens.eps, variant)
+        plan = nbody.Plan(ens.offsets, variant)
+        te = torch.from_numpy(ens.eps).to(dev)
         pairs = plan.pairs
     else:
         pos, vel, mass, spec = ics.workload(name)
@@ -109,16 +117,19 @@ def full_run(name, variant, steps=None):
     tp, tv, tm = (torch.from_numpy(x).to(dev) for x in (pos, vel, mass))
     pot = torch.empty_like(tm)
     diag = torch.empty((steps, nbody.DIAG_LEN), dtype=torch.float64, device=dev)
+    d0 = torch.empty((1, nbody.DIAG_LEN), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    # the initial forces, a zero-length step for the initial energy (same
+    # kernels), then the run
     if plan is not None:
-        acc, _ = plan.accel(tp, tm, 1.0, pot=pot)
+        acc, _ = plan.accel(tp, tm, te, 1.0, pot=pot)
+        nbody.step_batched(tp, tv, acc, tm, plan, te, 1.0, 0.0, 1, diag=d0, pot=pot)
+        nbody.step_batched(tp, tv, acc, tm, plan, te, 1.0, spec["dt"], steps, diag=diag, pot=pot)
     else:
         acc, _ = nbody.accel(tp, tm, eps, 1.0, variant, pot=pot)
-    # initial energy from the same kernels
-    d0 = torch.empty((1, nbody.DIAG_LEN), dtype=torch.float64, device=dev)
-    nbody.step(tp, tv, acc, tm, eps, 1.0, 0.0, 1, variant, plan=plan, diag=d0, pot=pot)
-    nbody.step(tp, tv, acc, tm, eps, 1.0, spec["dt"], steps, variant, plan=plan, diag=diag, pot=pot)
+        nbody.step(tp, tv, acc, tm, eps, 1.0, 0.0, 1, variant, diag=d0, pot=pot)
+        nbody.step(tp, tv, acc, tm, eps, 1.0, spec["dt"], steps, variant, diag=diag, pot=pot)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     d = diag.cpu().numpy()
@@ -157,7 +168,7 @@ PAPER_TIME_TO_SOLUTION_S = {"wormhole_n300_plus_host": 301.40, "cpu_2x_epyc_9124
 PAPER_ENERGY_TO_SOLUTION_KJ = {"wormhole_n300_plus_host": 71.56, "cpu_2x_epyc_9124": 128.89}
 
 
-def paper_run(variant, units=10.0, cpu_seconds=10.0):
+def paper_run(variant, units=10.0, cpu_seconds=10.0, readings=("steps", "units"), min_seconds=3.0):
     """The paper's representative run (Section 4) on one GPU: N = 102,400
     Plummer sphere, fourth-order Hermite with acceleration + jerk on the GPU
     and the FP64 update on the GPU. The paper does not define its "time
@@ -165,7 +176,9 @@ def paper_run(variant, units=10.0, cpu_seconds=10.0):
     workload's step. Time-to-solution spans the host's initial conditions,
     the upload, every force evaluation and update, and the download of the
     final state; energy-to-solution covers the same span (GPU energy counter,
-    host RAPL when readable)."""
+    host RAPL when readable). ``readings`` picks "steps" and/or "units";
+    ``cpu_seconds`` = 0 skips the CPU oracle's timing. Prints one JSON line
+    per reading and returns them."""
     import torch
 
     from oracle import cpu as ocpu
@@ -202,8 +215,13 @@ def paper_run(variant, units=10.0, cpu_seconds=10.0):
         wall = time.perf_counter() - t0
         return wall, t_ic, (pos, vel, mass, pf, vf), d, e0
 
-    readings = (("ten steps", spec["steps"]), (f"{units:g} time units", int(round(units / dt))))
-    for reading, steps in readings:
+    todo = []
+    if "steps" in readings:
+        todo.append(("ten steps", spec["steps"]))
+    if "units" in readings:
+        todo.append((f"{units:g} time units", int(round(units / dt))))
+    results = []
+    for reading, steps in todo:
         # A short run is repeated back to back (at least 3 times, about 3 s in
         # all) so that the GPU energy counter, which advances at its own
         # interval, spans it; time and energy are reported per run.
@@ -214,7 +232,7 @@ def paper_run(variant, units=10.0, cpu_seconds=10.0):
                 wall, t_ic, state, d, e0 = run_once(steps)
                 walls.append(wall)
                 ics_s.append(t_ic)
-                if len(walls) >= 3 and time.perf_counter() - t_all >= 3.0:
+                if len(walls) >= 3 and time.perf_counter() - t_all >= min_seconds:
                     break
                 if steps > 100:
                     break
@@ -253,11 +271,14 @@ def paper_run(variant, units=10.0, cpu_seconds=10.0):
                 "jerk_rel_rms": float(f"{orc.rel_rms(gj, rj):.3e}"),
                 "jerk_paper_metric": float(f"{orc.paper_metric(gj, rj):.3e}"),
             }
-            cb, _, _ = cpu_baseline(pos, mass, eps, cpu_seconds, vel=vel)
-            per_eval = float(n) * n / (cb["value"] * 1e9)
-            cb["time_to_solution_s_extrapolated"] = round(per_eval * (steps + 2), 1)
-            out["cpu_baseline"] = cb
+            if cpu_seconds > 0:
+                cb, _, _ = cpu_baseline(pos, mass, eps, cpu_seconds, vel=vel)
+                per_eval = float(n) * n / (cb["value"] * 1e9)
+                cb["time_to_solution_s_extrapolated"] = round(per_eval * (steps + 2), 1)
+                out["cpu_baseline"] = cb
         print(json.dumps(out), flush=True)
+        results.append(out)
+    return results
 
 
 def cpu_baseline(pos, mass, eps, budget_s, vel=None):
@@ -317,6 +338,8 @@ def cpu_baseline(pos, mass, eps, budget_s, vel=None):
         pairs = float(len(tgt)) * n
         sample = f"{len(tgt)} strided targets x {n} sources"
         refs = evaluate(gate)
+    # one whole evaluation, extrapolated from a target subset's rate
+    extrapolated = None if full_s <= 0.5 * budget_s else round(float(n) * n / (pairs / el), 2)
     what = "accelerations and potentials" if vel is None else "accelerations, jerks and potentials"
     return {
         "value": pairs / el / 1e9,
@@ -325,6 +348,7 @@ def cpu_baseline(pos, mass, eps, budget_s, vel=None):
         "kind": "oracle",
         "sample": f"{sample} ({pairs:.3e} FP64 pairs in {el:.1f} s; {what}; C + OpenMP, {threads} threads)",
         "cpu_model": _cpu_model(),
+        "full_evaluation_s_extrapolated": extrapolated,
         "numpy_single_thread": _numpy_oracle_rate(pos, mass, eps, vel),
     }, gate, refs
 
@@ -415,12 +439,17 @@ def main():
     dev = torch.device("cuda:0")
     name = args.workload
     variant = args.variant or DEFAULT_VARIANT[name]
-    plan = None
+    hermite = args.hermite
+    if hermite and name == "ensemble_512":
+        print(json.dumps({"error": "--hermite runs on a single system, not the cluster ensemble"}))
+        sys.exit(2)
+    plan = plain_plan = te = None
     if name == "ensemble_512":
         ens, spec = ics.workload(name)
         pos, vel, mass = ens.pos, ens.vel, ens.mass
         eps = 0.0
-        plan = nbody.Plan(ens.offsets, ens.eps, variant)
+        plan = nbody.Plan(ens.offsets, variant)
+        te = torch.from_numpy(ens.eps).to(dev)
         pairs_per_eval = plan.pairs
         n = len(mass)
     else:
@@ -430,21 +459,23 @@ def main():
         pairs_per_eval = float(n) * float(n)
     dt = spec["dt"]
 
-    hermite = args.hermite
-    if hermite and plan is not None:
-        print(json.dumps({"error": "--hermite runs on a single system, not the cluster ensemble"}))
-        sys.exit(2)
     tp = torch.from_numpy(pos).to(dev)
     tv = torch.from_numpy(vel).to(dev)
     tm = torch.from_numpy(mass).to(dev)
     pot = torch.empty_like(tm)
-    jerk = None
-    if plan is not None:
-        acc, _ = plan.accel(tp, tm, 1.0, pot=pot)
-    elif hermite:
-        acc, jerk, _ = nbody.accel_jerk(tp, tv, tm, eps, 1.0, variant, pot=pot)
-    else:
-        acc, _ = nbody.accel(tp, tm, eps, 1.0, variant, pot=pot)
+    acc = torch.empty_like(tp)
+    jerk = torch.empty_like(tp) if hermite else None
+
+    def force(form=variant, on_plan=None):
+        """One force (or acceleration + jerk) evaluation on the current state."""
+        if on_plan is not None:
+            on_plan.accel(tp, tm, te, 1.0, acc=acc, pot=pot)
+        elif hermite:
+            nbody.accel_jerk(tp, tv, tm, eps, 1.0, form, acc=acc, jerk=jerk, pot=pot)
+        else:
+            nbody.accel(tp, tm, eps, 1.0, form, acc=acc, pot=pot)
+
+    force(on_plan=plan)
     torch.cuda.synchronize()
     acc0 = acc.cpu().numpy()
     pot0 = pot.cpu().numpy()
@@ -455,20 +486,17 @@ def main():
     def one_step():
         if hermite:
             nbody.step_hermite(tp, tv, acc, jerk, tm, eps, 1.0, dt, 1, variant, diag=diag, pot=pot)
+        elif plan is not None:
+            nbody.step_batched(tp, tv, acc, tm, plan, te, 1.0, dt, 1, diag=diag, pot=pot)
         else:
-            nbody.step(tp, tv, acc, tm, eps, 1.0, dt, 1, variant, plan=plan, diag=diag, pot=pot)
+            nbody.step(tp, tv, acc, tm, eps, 1.0, dt, 1, variant, diag=diag, pot=pot)
 
     # Bring the GPU out of its idle clock state before the warm-up steps: force
     # evaluations on the same inputs (no state change) for about 0.3 s.
     t_ramp = time.perf_counter() + 0.3
     while time.perf_counter() < t_ramp:
-        for _ in range(10):
-            if plan is not None:
-                plan.accel(tp, tm, 1.0, acc=acc, pot=pot)
-            elif hermite:
-                nbody.accel_jerk(tp, tv, tm, eps, 1.0, variant, acc=acc, jerk=jerk, pot=pot)
-            else:
-                nbody.accel(tp, tm, eps, 1.0, variant, acc=acc, pot=pot)
+        for _ in range(10 if pairs_per_eval < 1e11 else 1):
+            force(on_plan=plan)
         torch.cuda.synchronize()
 
     for _ in range(args.warmup):
@@ -493,32 +521,30 @@ def main():
     launches, kernel_ms = nbody.timing_read()
     nbody.timing_enable(False)
 
-    # The force evaluation alone (pack or staging, pair kernel, split
-    # combine, epilogue), repeated on the same inputs: median and minimum.
-    force_ms = []
-    for _ in range(max(args.steps, 5)):
-        a_ev = torch.cuda.Event(enable_timing=True)
-        b_ev = torch.cuda.Event(enable_timing=True)
-        a_ev.record(stream)
-        if plan is not None:
-            plan.accel(tp, tm, 1.0, acc=acc, pot=pot)
-        elif hermite:
-            nbody.accel_jerk(tp, tv, tm, eps, 1.0, variant, acc=acc, jerk=jerk, pot=pot)
-        else:
-            nbody.accel(tp, tm, eps, 1.0, variant, acc=acc, pot=pot)
-        b_ev.record(stream)
-        b_ev.synchronize()
-        force_ms.append(a_ev.elapsed_time(b_ev))
-
-    if plan is not None:
-        # The batched force kernel runs inside the graph replay: time it
-        # eagerly, bracketed the same way, on the same stream and inputs.
+    def evaluations(reps, form=variant, on_plan=None):
+        """The force evaluation alone (ordering or pack, pair kernel, split
+        combine, epilogue), repeated on the same inputs: per-evaluation times
+        and the pair kernel's own (launches, total ms) from the library's
+        event brackets."""
+        times = []
         nbody.timing_enable(True)
-        for _ in range(args.steps):
-            plan.accel(tp, tm, 1.0, acc=acc, pot=pot)
-        torch.cuda.synchronize()
-        launches, kernel_ms = nbody.timing_read()
+        for _ in range(reps):
+            a_ev = torch.cuda.Event(enable_timing=True)
+            b_ev = torch.cuda.Event(enable_timing=True)
+            a_ev.record(stream)
+            force(form, on_plan)
+            b_ev.record(stream)
+            b_ev.synchronize()
+            times.append(a_ev.elapsed_time(b_ev))
+        kern = nbody.timing_read()
         nbody.timing_enable(False)
+        return times, kern
+
+    force_ms, kern_eval = evaluations(max(args.steps, 5), on_plan=plan)
+    if plan is not None:
+        # The batched force kernel runs inside the graph replay: its duration
+        # comes from the same kernels launched eagerly on the same stream.
+        launches, kernel_ms = kern_eval
 
     traffic = None
     if hermite:
@@ -527,11 +553,32 @@ def main():
     elif plan is None:
         cfg, split = nbody.tune_get(variant, n)
         traffic = MEASURED_TRAFFIC.get((name, variant, cfg, split))
+    else:
+        traffic = MEASURED_TRAFFIC.get((name, variant, "batched"))
     ms_per_step = ms_total / args.steps
     value = pairs_per_eval / (ms_per_step * 1e-3) / 1e9
     kernel_avg_ms = kernel_ms / max(launches, 1)
     flops = FLOPS_PER_JERK_INTERACTION if hermite else FLOPS_PER_INTERACTION
     achieved = flops * pairs_per_eval / (kernel_avg_ms * 1e-3) / 1e12
+
+    # The plain FP32 kernel on the same inputs (the state the timed steps
+    # left), the reference point the compensated form is reported against.
+    plain = None
+    if variant == "comp":
+        plain_plan = nbody.Plan(ens.offsets, "plain") if plan is not None else None
+        force("plain", plain_plan)   # first use: code objects, workspace
+        torch.cuda.synchronize()
+        p_ms, (p_l, p_k) = evaluations(max(3, min(args.steps, 10)), "plain", plain_plan)
+        p_avg = p_k / max(p_l, 1)
+        p_ach = flops * pairs_per_eval / (p_avg * 1e-3) / 1e12
+        plain = {
+            "what": "the plain FP32 kernel on the same inputs and GPU, repeated evaluations",
+            "kernel_avg_ms": round(p_avg, 4), "kernel_launches": p_l,
+            "achieved_TFLOPs": round(p_ach, 2), "frac": round(p_ach / FP32_VECTOR_PEAK_TFLOPS, 4),
+            "evaluation_ms_median": round(float(np.median(p_ms)), 4),
+            "G_pair_per_s_median": round(pairs_per_eval / (float(np.median(p_ms)) * 1e-3) / 1e9, 1),
+            "compensated_kernel_over_plain": round(p_avg / kernel_avg_ms, 4),
+        }
 
     out = {
         "metric": ("G pair-interactions/s (acceleration + jerk) and % FP32 VALU peak at rel-RMS "
@@ -552,7 +599,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{name}: " + (
-                f"{len(plan.eps)} Plummer clusters, N_total={n}" if plan is not None
+                f"{plan.K} Plummer clusters, N_total={n}, eps_k=4/N_k" if plan is not None
                 else f"Plummer sphere N={n}" + (" Kroupa masses" if name == "kroupa_1m" else "")
                 + f", eps={eps}") + f", dt={dt}, one "
                 + ("fourth-order Hermite" if hermite else "KDK") + " step with diagnostics",
@@ -562,7 +609,7 @@ def main():
         },
         "force_evaluation": {
             "what": "one " + ("acceleration + jerk" if hermite else "force") + " evaluation alone "
-                    "(pack, pair kernel, split combine, FP64 epilogue), repeated",
+                    "(ordering or pack, pair kernel, split combine, FP64 epilogue), repeated",
             "ms_median": round(float(np.median(force_ms)), 4),
             "ms_min": round(float(np.min(force_ms)), 4),
             "G_pair_per_s_median": round(pairs_per_eval / (float(np.median(force_ms)) * 1e-3) / 1e9, 1),
@@ -579,6 +626,8 @@ def main():
             "flops_per_interaction": flops,
         },
     }
+    if plain is not None:
+        out["plain_same_inputs"] = plain
     try:
         out["device"] = device_info()
     except Exception as e:  # informational only
@@ -606,14 +655,27 @@ def main():
             **({"jerk_rel_rms": float(f"{orc.rel_rms(jerk0[tgt], refs[2]):.3e}"),
                 "jerk_paper_metric": float(f"{orc.paper_metric(jerk0[tgt], refs[2]):.3e}")} if hermite else {}),
             "targets": int(len(tgt)),
+            "where": "the initial state, before the warm-up steps",
             "gate_rel_rms_1e-5": bool(acc_err <= 1e-5),
         }
+        if plain is not None:
+            # the plain kernel's error on the same targets of the initial state
+            tp.copy_(torch.from_numpy(pos))
+            force("plain", plain_plan)
+            torch.cuda.synchronize()
+            if plan is not None:
+                pa = acc.cpu().numpy()[s:e][tgt]
+            else:
+                pa = acc.cpu().numpy()[tgt]
+            plain["acc_rel_rms"] = float(f"{orc.rel_rms(pa, ref_a):.3e}")
+            plain["acc_max_rel"] = float(f"{orc.max_rel(pa, ref_a):.3e}")
         if acc_err > 1e-5:
             out["value"] = None
             out["note"] = "accuracy gate failed: throughput not reported"
     print(json.dumps(out), flush=True)
-    if plan is not None:
-        plan.close()
+    for p_ in (plan, plain_plan):
+        if p_ is not None:
+            p_.close()
 
 
 if __name__ == "__main__":

@@ -110,53 +110,96 @@ nbody_status nbody_accel(const double *pos, const double *mass, int64_t n,
                          double *acc, double *pot,
                          void *ws, size_t ws_bytes, void *stream);
 
-/* n_steps kick-drift-kick leapfrog steps (all FP64 on the GPU, forces by the
- * chosen variant). Per step: v += dt/2 a; x += dt v; a = A(x); v += dt/2 a.
+/* Allocation-free nbody_accel, for callers that cannot allocate device
+ * memory or hand the library a workspace: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation.
+ * Same arguments, results and errors as nbody_accel, without ws/ws_bytes:
+ * its workspace is a 64 MiB static device array inside the library, which
+ * every GPU the library runs on holds until the process ends. The first call
+ * on a device looks up that device's copy; no call allocates or frees.
+ * Limits: n <= 1,676,064 (NBODY_FP32_PLAIN) and n <= 536,480
+ * (NBODY_FP32_COMP); a larger n is EINVAL and names the limit. Where the
+ * tuned grid j-split's partial sums do not fit, a smaller split is used, so
+ * results are bitwise equal to nbody_accel's at most sizes and otherwise
+ * differ only in summation order (within the same tolerances).
+ * All calls on one GPU share that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (two streams, two host threads)
+ * race and corrupt each other's results; the caller must order them. */
+nbody_status nbody_accel_noalloc(const double *pos, const double *mass, int64_t n,
+                                 double eps, double G, int32_t variant,
+                                 double *acc, double *pot, void *stream);
+
+/* n_steps kick-drift-kick leapfrog steps of a single system (all FP64 on the
+ * GPU, forces by the chosen variant). Per step: v += dt/2 a; x += dt v;
+ * a = A(x); v += dt/2 a.
  *   pos, vel [n][3] f64 in/out; acc [n][3] f64 in/out: on entry it must hold
  *   A(pos) (call nbody_accel once first), on return A(pos_final).
  *   pot [n] f64 out (potentials at the final positions) or NULL.
  *   mass [n] f64 in. eps, G, variant as for nbody_accel; dt finite;
  *   n_steps >= 0.
- *   plan: NULL for a single system; otherwise a plan from nbody_plan_create
- *   whose clusters cover exactly n particles, in which case eps is ignored
- *   (each cluster uses its own) and variant must match the plan's.
+ *   plan: must be NULL. (Batched clusters are stepped by nbody_step_batched,
+ *   which takes the per-cluster softenings; a non-NULL plan is EINVAL.)
  *   diag [n_steps][NBODY_DIAG_LEN] f64 out or NULL: one row after each step.
- *   ws as for nbody_accel (nbody_workspace_bytes(n, K, variant)).
- * With a plan, each step is one replay of a HIP graph the plan captures on
- * first use for this set of pointers and scalars. */
+ *   ws as for nbody_accel (nbody_workspace_bytes(n, 1, variant)). */
 nbody_status nbody_step(double *pos, double *vel, double *acc, double *pot,
                         const double *mass, int64_t n, double eps, double G,
                         double dt, int32_t n_steps, int32_t variant,
-                        nbody_plan *plan, double *diag,
+                        const nbody_plan *plan, double *diag,
                         void *ws, size_t ws_bytes, void *stream);
 
-/* Build a plan for K independent clusters. Cluster k owns particles
- * [offsets_host[k], offsets_host[k+1]) and is softened by eps_host[k];
- * clusters exert no force on one another.
- *   offsets_host [K+1] int64 host, offsets_host[0] = 0, non-decreasing.
- *   eps_host [K] f64 host, each >= 0 and finite.
- *   variant as above. tune_path: a tuning file written by the autotuner, or
- *   NULL for built-in defaults (the NBODY_TUNE environment variable, if set,
- *   names a file used when tune_path is NULL).
- * Allocates device memory for the work list and the graph. Returns NULL on
- * error (see nbody_last_error). */
+/* Build a plan for K independent clusters (the force equation of Section 3
+ * applied within each cluster; clusters exert no force on one another).
+ * Cluster k owns particles [offsets_host[k], offsets_host[k+1]).
+ *   offsets_host [K+1] int64 host, offsets_host[0] = 0, non-decreasing;
+ *   offsets_host[K] + 16 K < 2^31.
+ *   variant as above; the batched calls made with the plan must use it.
+ *   tune_path: a tuning file written by the autotuner (its "batched" lines
+ *   pick the plan's kernel mode per cluster size class; other lines are
+ *   checked and ignored), or NULL for the process-wide table (built-in, then
+ *   NBODY_TUNE, then nbody_tune_load). The file affects this plan only.
+ * The per-cluster softenings are not part of the plan: every batched call
+ * takes them (eps_k), so one plan serves any softenings.
+ * Allocates device memory for the work list and a capture stream on the
+ * current device. Returns NULL on error (see nbody_last_error). */
 nbody_plan *nbody_plan_create(const int64_t *offsets_host, int32_t K,
-                              const double *eps_host, int32_t variant,
-                              const char *tune_path);
+                              int32_t variant, const char *tune_path);
 
 /* Free a plan (NULL is a no-op). The caller must ensure no enqueued work
  * still uses it. */
 void nbody_plan_destroy(nbody_plan *plan);
 
 /* Accelerations and potentials of every cluster of `plan`, each from its own
- * members only, in one persistent-kernel launch.
+ * members only and softened by its own eps_k[k], in one persistent-kernel
+ * launch per kernel mode.
  *   pos [n_total][3], mass [n_total] in; acc [n_total][3] out; pot [n_total]
- *   out or NULL; n_total = offsets_host[K]. G finite.
- *   ws: ws_bytes >= nbody_workspace_bytes(n_total, K, variant). */
+ *   out or NULL; n_total = offsets_host[K] of the plan.
+ *   eps_k [K] f64 in, DEVICE memory, 8-byte aligned, read by the kernel
+ *   (its values are not checked on the host: each should be finite and
+ *   >= 0; eps_k[k] = 0 is the unsoftened sum for cluster k, a NaN makes that
+ *   cluster's outputs NaN). G finite. variant must equal the plan's.
+ *   ws: ws_bytes >= nbody_workspace_bytes(n_total, K, variant).
+ * Errors: EINVAL (NULL plan, NULL eps_k for a non-empty plan, misaligned
+ * eps_k, variant differing from the plan's, bad G, NULL or overlapping
+ * arrays), ENOTSUP (unknown variant), EWORKSPACE, EHIP. */
 nbody_status nbody_accel_batched(const double *pos, const double *mass,
-                                 nbody_plan *plan, double G,
+                                 const nbody_plan *plan, const double *eps_k,
+                                 double G, int32_t variant,
                                  double *acc, double *pot,
                                  void *ws, size_t ws_bytes, void *stream);
+
+/* n_steps kick-drift-kick steps of every cluster of `plan` (the step of
+ * nbody_step, the forces of nbody_accel_batched with eps_k).
+ *   n must equal the plan's n_total; eps_k, variant as for
+ *   nbody_accel_batched; other arguments as for nbody_step. The diagnostics
+ *   rows sum over all clusters.
+ * Each step is one replay of a HIP graph the plan captures on first use for
+ * this set of pointers (eps_k included) and scalars; eps_k's contents are
+ * read at every replay, so they may change between calls. */
+nbody_status nbody_step_batched(double *pos, double *vel, double *acc, double *pot,
+                                const double *mass, int64_t n, const nbody_plan *plan,
+                                const double *eps_k, double G, double dt,
+                                int32_t n_steps, int32_t variant, double *diag,
+                                void *ws, size_t ws_bytes, void *stream);
 
 /* Number of particles and clusters a plan covers, and its variant. */
 int64_t nbody_plan_total(const nbody_plan *plan);

@@ -136,6 +136,7 @@ def tune_batched(variant, c, reps=5, log=None):
     pos, mass, offsets, eps = _class_ensemble(c, k, 77 + c)
     tp = torch.from_numpy(pos).cuda()
     tm = torch.from_numpy(mass).cuda()
+    te = torch.from_numpy(eps).cuda()
     acc = torch.empty_like(tp)
     pot = torch.empty_like(tm)
     best = None
@@ -145,13 +146,12 @@ def tune_batched(variant, c, reps=5, log=None):
             f.write(f"batched {nbody.VARIANTS[variant]} {c} {mode}\n")
             path = f.name
         try:
-            plan = nbody.Plan(offsets, eps, variant, tune_path=path)
-            ms = _time(lambda: plan.accel(tp, tm, 1.0, acc=acc, pot=pot), reps)
+            plan = nbody.Plan(offsets, variant, tune_path=path)
+            ms = _time(lambda: plan.accel(tp, tm, te, 1.0, acc=acc, pot=pot), reps)
             rate = plan.pairs / (ms * 1e-3) / 1e9
             plan.close()
         finally:
             os.unlink(path)
-            nbody.tune_reset()
         rows.append({"variant": variant, "class": c, "mode": mode, "clusters": k, "ms": round(ms, 4),
                      "G_int_per_s": round(rate, 1)})
         if log:

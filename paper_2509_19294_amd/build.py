@@ -42,7 +42,7 @@ def hipcc() -> str:
 def sources():
     return [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "kernels_jerk.hip"),
             os.path.join(CSRC, "kernels_order.hip"), os.path.join(CSRC, "kernels_nf.hip"),
-            os.path.join(CSRC, "kernels_nf_jerk.hip"),
+            os.path.join(CSRC, "kernels_nf_jerk.hip"), os.path.join(CSRC, "noalloc.hip"),
             os.path.join(CSRC, "abi.cpp")]
 
 

@@ -52,15 +52,18 @@ int64_t packed_entries(int64_t n, int32_t n_clusters) {
   return slots > single ? slots : single;
 }
 
-WsLayout ws_layout(int64_t n, int32_t variant, int32_t n_clusters = 1) {
+// `split_cap` bounds the grid j-splits the partial-sum region holds (the
+// allocation-free entry point passes what its static scratch can take).
+WsLayout ws_layout(int64_t n, int32_t variant, int32_t n_clusters = 1, int split_cap = nb::kMaxSplit) {
   WsLayout L{};
   const size_t un = static_cast<size_t>(n);
   const size_t jw = variant == NBODY_FP32_COMP ? 2 : 1;
+  const int splits = std::min(nb::max_split(n), std::max(split_cap, 1));
   size_t off = 0;
   L.packed = off;
   off += align_up(static_cast<size_t>(packed_entries(n, n_clusters)) * jw * sizeof(float4));
   L.part = off;
-  off += align_up(static_cast<size_t>(nb::max_split(n)) * un * jw * sizeof(float4));
+  off += align_up(static_cast<size_t>(splits) * un * jw * sizeof(float4));
   L.pot = off;
   off += align_up(un * sizeof(double));
   L.diag = off;
@@ -98,9 +101,15 @@ struct SingleTune {
 
 std::mutex g_tune_mu;
 SingleTune g_single[2][kClasses];
-int g_batched[2][kClasses];
 bool g_tune_init = false;
 int g_forced[2][kClasses];  // -1 = none
+
+// Batched modes per variant and size class. The process-wide table is what a
+// new plan starts from; a plan created with a tuning file keeps its own copy.
+struct BatchedTable {
+  int mode[2][kClasses];
+};
+BatchedTable g_batched;
 
 int size_class(int64_t n) {
   int c = 0;
@@ -133,7 +142,7 @@ void tune_defaults() {
       const int tc = c < 10 ? 0 : (c > 20 ? 10 : c - 10);
       g_single[v][c] = kTuned[v][tc];
       const int bc = c < 8 ? 0 : (c > 13 ? 5 : c - 8);
-      g_batched[v][c] = kTunedBatched[v][bc];
+      g_batched.mode[v][c] = kTunedBatched[v][bc];
       g_forced[v][c] = -1;
       g_jerk[v][c] = kTunedJerk[v][tc];
     }
@@ -141,9 +150,17 @@ void tune_defaults() {
   }
 }
 
-nbody_status tune_load_locked(const char *path) {
+// Reads a tuning file. Lines: "single v class cfg split", "batched v class
+// mode", "jerk v class shape split"; '#' starts a comment. With `only_batched`
+// (a plan's own file) the single and jerk lines are checked but not applied.
+// Nothing is applied unless the whole file parses.
+nbody_status tune_parse(const char *path, BatchedTable &batched, bool only_batched) {
   FILE *f = std::fopen(path, "r");
   if (!f) return fail(NBODY_EINVAL, "cannot open tuning file '%s'", path);
+  struct Entry {
+    int kind, v, c, a, b;
+  };
+  std::vector<Entry> entries;
   char line[256];
   int lineno = 0;
   while (std::fgets(line, sizeof(line), f)) {
@@ -161,27 +178,37 @@ nbody_status tune_load_locked(const char *path) {
         std::fclose(f);
         return fail(NBODY_EINVAL, "tuning file '%s' line %d: bad single entry", path, lineno);
       }
-      g_single[v][c] = SingleTune{a, b};
+      entries.push_back({0, v, c, a, b});
     } else if (std::strcmp(kind, "batched") == 0) {
       if (a < 0 || a >= nb::batched_mode_count()) {
         std::fclose(f);
         return fail(NBODY_EINVAL, "tuning file '%s' line %d: bad batched entry", path, lineno);
       }
-      g_batched[v][c] = a;
+      entries.push_back({1, v, c, a, 0});
     } else if (std::strcmp(kind, "jerk") == 0) {
       if (a < 0 || a >= nb::jerk_shape_count(v == NBODY_FP32_COMP) || b < 0 || b > nb::kMaxSplit) {
         std::fclose(f);
         return fail(NBODY_EINVAL, "tuning file '%s' line %d: bad jerk entry", path, lineno);
       }
-      g_jerk[v][c] = SingleTune{a, b};
+      entries.push_back({2, v, c, a, b});
     } else {
       std::fclose(f);
       return fail(NBODY_EINVAL, "tuning file '%s' line %d: unknown kind", path, lineno);
     }
   }
   std::fclose(f);
+  for (const Entry &e : entries) {
+    if (e.kind == 1)
+      batched.mode[e.v][e.c] = e.a;
+    else if (!only_batched && e.kind == 0)
+      g_single[e.v][e.c] = SingleTune{e.a, e.b};
+    else if (!only_batched && e.kind == 2)
+      g_jerk[e.v][e.c] = SingleTune{e.a, e.b};
+  }
   return NBODY_OK;
 }
+
+nbody_status tune_load_locked(const char *path) { return tune_parse(path, g_batched, false); }
 
 void tune_init_locked() {
   if (g_tune_init) return;
@@ -215,10 +242,11 @@ SingleTune jerk_tune(int32_t variant, int64_t n) {
   return t;
 }
 
-int batched_tune(int32_t variant, int64_t nk) {
+// The process-wide batched table (a new plan's starting point).
+BatchedTable batched_table() {
   std::lock_guard<std::mutex> g(g_tune_mu);
   tune_init_locked();
-  return g_batched[variant][size_class(nk)];
+  return g_batched;
 }
 
 // ---------------------------------------------------------------------------
@@ -278,8 +306,8 @@ nbody_status check_scalars(double eps, double G) {
 }
 
 nbody_status check_ws(void *ws, size_t ws_bytes, int64_t n, int32_t variant,
-                      int32_t n_clusters = 1) {
-  const size_t need = ws_layout(n, variant, n_clusters).total;
+                      int32_t n_clusters = 1, int split_cap = nb::kMaxSplit) {
+  const size_t need = ws_layout(n, variant, n_clusters, split_cap).total;
   if (!ws) return fail(NBODY_EWORKSPACE, "workspace is NULL (need %zu bytes)", need);
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(NBODY_EWORKSPACE, "workspace must be 256-byte aligned");
   if (ws_bytes < need) return fail(NBODY_EWORKSPACE, "workspace of %zu bytes < %zu required", ws_bytes, need);
@@ -287,10 +315,12 @@ nbody_status check_ws(void *ws, size_t ws_bytes, int64_t n, int32_t variant,
 }
 
 hipError_t enqueue_accel(const double *pos, const double *mass, int64_t n, double eps, double G,
-                         int32_t variant, double *acc, double *pot, void *ws, hipStream_t st) {
+                         int32_t variant, double *acc, double *pot, void *ws, hipStream_t st,
+                         int split_cap = nb::kMaxSplit) {
   if (n <= 0) return hipSuccess;
-  const WsLayout L = ws_layout(n, variant);
+  const WsLayout L = ws_layout(n, variant, 1, split_cap);
   SingleTune t = single_tune(variant, n);
+  t.split = std::min(t.split, std::max(split_cap, 1));
   const bool comp = variant == NBODY_FP32_COMP;
   float4 *packed = at<float4>(ws, L.packed);
   // the spatial order indexes particles with 32-bit integers
@@ -394,11 +424,9 @@ struct nbody_plan {
   int32_t variant = 0;
   int64_t n_total = 0;
   std::vector<int64_t> offsets;
-  std::vector<double> eps;
   int32_t n_items = 0;
   double pairs = 0.0;
   nb::Item *d_items = nullptr;
-  double *d_eps = nullptr;
   int32_t *d_slot_src = nullptr;    // slot layout of the packed sources
   int32_t *d_slot_frame = nullptr;
   int64_t n_slots = 0;
@@ -407,22 +435,25 @@ struct nbody_plan {
   int32_t seg_end[nb::kBatchedModes] = {};
   int grid[nb::kBatchedModes] = {};
   int device = 0;
-  hipStream_t capture = nullptr;
-  // Cached graph of one KDK step and the arguments it was captured with.
-  hipGraphExec_t exec = nullptr;
-  const void *key[9] = {};
-  double key_g = 0, key_dt = 0;
+  // Cache of one captured KDK step and the arguments it was captured with.
+  // It changes behind a const plan pointer (a cache, not part of the plan's
+  // meaning), which is why calls sharing a plan must be ordered.
+  mutable hipStream_t capture = nullptr;
+  mutable hipGraphExec_t exec = nullptr;
+  mutable const void *key[10] = {};
+  mutable double key_g = 0, key_dt = 0;
 };
 
 namespace {
 
-hipError_t enqueue_batched(const double *pos, const double *mass, nbody_plan *p, double G,
-                           double *acc, double *pot, void *ws, hipStream_t st) {
+hipError_t enqueue_batched(const double *pos, const double *mass, const nbody_plan *p,
+                           const double *eps_k, double G, double *acc, double *pot, void *ws,
+                           hipStream_t st) {
   const WsLayout L = ws_layout(p->n_total, p->variant, p->K);
   nb::BatchedArgs b{};
   b.items = p->d_items;
   b.n_items = p->n_items;
-  b.eps_k = p->d_eps;
+  b.eps_k = eps_k;
   b.slot_src = p->d_slot_src;
   b.slot_frame = p->d_slot_frame;
   b.n_slots = p->n_slots;
@@ -440,17 +471,20 @@ hipError_t enqueue_batched(const double *pos, const double *mass, nbody_plan *p,
   return e;
 }
 
-// One KDK step: kick-drift, forces, kick (+ diagnostics row).
+// One KDK step: kick-drift, forces, kick (+ diagnostics row). `plan` NULL:
+// a single system softened by eps; otherwise the plan's clusters softened by
+// eps_k.
 hipError_t enqueue_step(double *pos, double *vel, double *acc, double *pot, const double *mass,
                         int64_t n, double eps, double G, double dt, int32_t variant,
-                        nbody_plan *plan, double *diag, void *ws, hipStream_t st) {
+                        const nbody_plan *plan, const double *eps_k, double *diag, void *ws,
+                        hipStream_t st) {
   const WsLayout L = ws_layout(n, variant, plan ? plan->K : 1);
   const double h = 0.5 * dt;
   hipError_t e = nb::launch_kick_drift(pos, vel, acc, n, h, dt, st);
   if (e != hipSuccess) return e;
   double *potw = pot ? pot : (diag ? at<double>(ws, L.pot) : nullptr);
   if (plan)
-    e = enqueue_batched(pos, mass, plan, G, acc, potw, ws, st);
+    e = enqueue_batched(pos, mass, plan, eps_k, G, acc, potw, ws, st);
   else
     e = enqueue_accel(pos, mass, n, eps, G, variant, acc, potw, ws, st);
   if (e != hipSuccess) return e;
@@ -462,7 +496,62 @@ hipError_t enqueue_step(double *pos, double *vel, double *acc, double *pot, cons
   return nb::launch_kick(vel, acc, n, h, st);
 }
 
+// Host checks of a batched call's plan, variant and per-cluster softenings.
+nbody_status check_batched(const nbody_plan *plan, int32_t variant, const double *eps_k) {
+  if (!plan) return fail(NBODY_EINVAL, "plan is NULL");
+  if (!valid_variant(variant)) return fail(NBODY_ENOTSUP, "unknown variant %d", variant);
+  if (variant != plan->variant)
+    return fail(NBODY_EINVAL, "variant %d does not match the plan's %d", variant, plan->variant);
+  if (plan->n_total > 0 && !eps_k) return fail(NBODY_EINVAL, "eps_k must be non-NULL");
+  if (reinterpret_cast<uintptr_t>(eps_k) % alignof(double) != 0)
+    return fail(NBODY_EINVAL, "eps_k must be 8-byte aligned");
+  return NBODY_OK;
+}
+
 }  // namespace
+
+namespace nb {
+
+int32_t set_error(int32_t status, const char *msg) { return fail(status, "%s", msg); }
+
+int32_t check_accel_args(const double *pos, const double *mass, int64_t n, double eps, double G,
+                         int32_t variant, const double *acc, const double *pot) {
+  g_err.clear();
+  if (n < 0) return fail(NBODY_EINVAL, "n must be >= 0 (got %lld)", static_cast<long long>(n));
+  if (!valid_variant(variant)) return fail(NBODY_ENOTSUP, "unknown variant %d", variant);
+  nbody_status st = check_scalars(eps, G);
+  if (st != NBODY_OK) return st;
+  if (n == 0) return NBODY_OK;
+  if (!pos || !mass || !acc) return fail(NBODY_EINVAL, "pos, mass and acc must be non-NULL");
+  const size_t b3 = static_cast<size_t>(n) * 3 * sizeof(double), b1 = static_cast<size_t>(n) * sizeof(double);
+  if (overlap(acc, b3, pos, b3) || overlap(acc, b3, mass, b1) || overlap(pot, b1, pos, b3) ||
+      overlap(pot, b1, mass, b1) || overlap(pot, b1, acc, b3))
+    return fail(NBODY_EINVAL, "output arrays overlap inputs or each other");
+  return NBODY_OK;
+}
+
+size_t accel_ws_bytes(int64_t n, int32_t variant, int split_cap) {
+  return ws_layout(n, variant, 1, split_cap).total;
+}
+
+int accel_tuned_split(int32_t variant, int64_t n) {
+  return std::min(single_tune(variant, n).split, max_split(n));
+}
+
+int32_t accel_entry(const double *pos, const double *mass, int64_t n, double eps, double G,
+                    int32_t variant, double *acc, double *pot, void *ws, size_t ws_bytes,
+                    int split_cap, void *stream) {
+  nbody_status st = check_accel_args(pos, mass, n, eps, G, variant, acc, pot);
+  if (st != NBODY_OK || n == 0) return st;
+  st = check_ws(ws, ws_bytes, n, variant, 1, split_cap);
+  if (st != NBODY_OK) return st;
+  const hipError_t e = enqueue_accel(pos, mass, n, eps, G, variant, acc, pot, ws,
+                                     static_cast<hipStream_t>(stream), split_cap);
+  if (e != hipSuccess) return hip_fail(e, "nbody_accel launch");
+  return NBODY_OK;
+}
+
+}  // namespace nb
 
 extern "C" {
 
@@ -478,30 +567,14 @@ size_t nbody_workspace_bytes(int64_t n_total, int32_t n_clusters, int32_t varian
 nbody_status nbody_accel(const double *pos, const double *mass, int64_t n, double eps, double G,
                          int32_t variant, double *acc, double *pot, void *ws, size_t ws_bytes,
                          void *stream) {
-  g_err.clear();
-  if (n < 0) return fail(NBODY_EINVAL, "n must be >= 0 (got %lld)", static_cast<long long>(n));
-  if (!valid_variant(variant)) return fail(NBODY_ENOTSUP, "unknown variant %d", variant);
-  nbody_status st = check_scalars(eps, G);
-  if (st != NBODY_OK) return st;
-  if (n == 0) return NBODY_OK;
-  if (!pos || !mass || !acc) return fail(NBODY_EINVAL, "pos, mass and acc must be non-NULL");
-  const size_t b3 = static_cast<size_t>(n) * 3 * sizeof(double), b1 = static_cast<size_t>(n) * sizeof(double);
-  if (overlap(acc, b3, pos, b3) || overlap(acc, b3, mass, b1) || overlap(pot, b1, pos, b3) ||
-      overlap(pot, b1, mass, b1) || overlap(pot, b1, acc, b3))
-    return fail(NBODY_EINVAL, "output arrays overlap inputs or each other");
-  st = check_ws(ws, ws_bytes, n, variant);
-  if (st != NBODY_OK) return st;
-  const hipError_t e = enqueue_accel(pos, mass, n, eps, G, variant, acc, pot, ws,
-                                     static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return hip_fail(e, "nbody_accel launch");
-  return NBODY_OK;
+  return nb::accel_entry(pos, mass, n, eps, G, variant, acc, pot, ws, ws_bytes, nb::kMaxSplit, stream);
 }
 
-nbody_plan *nbody_plan_create(const int64_t *offsets_host, int32_t K, const double *eps_host,
-                              int32_t variant, const char *tune_path) {
+nbody_plan *nbody_plan_create(const int64_t *offsets_host, int32_t K, int32_t variant,
+                              const char *tune_path) {
   g_err.clear();
-  if (!offsets_host || !eps_host) {
-    fail(NBODY_EINVAL, "offsets and eps must be non-NULL");
+  if (!offsets_host) {
+    fail(NBODY_EINVAL, "offsets must be non-NULL");
     return nullptr;
   }
   if (K < 1) {
@@ -521,26 +594,20 @@ nbody_plan *nbody_plan_create(const int64_t *offsets_host, int32_t K, const doub
       fail(NBODY_EINVAL, "offsets must be non-decreasing (at %d)", k);
       return nullptr;
     }
-    if (!std::isfinite(eps_host[k]) || eps_host[k] < 0.0) {
-      fail(NBODY_EINVAL, "eps[%d] must be finite and >= 0", k);
-      return nullptr;
-    }
   }
   if (offsets_host[K] + static_cast<int64_t>(nb::kSlotAlign) * K >= (int64_t{1} << 31)) {
     fail(NBODY_ENOTSUP, "batched plans hold fewer than 2^31 particles");
     return nullptr;
   }
-  if (tune_path) {
-    std::lock_guard<std::mutex> g(g_tune_mu);
-    tune_init_locked();
-    if (tune_load_locked(tune_path) != NBODY_OK) return nullptr;
-  }
+  // The plan's own modes: the process-wide table, overridden by the batched
+  // lines of tune_path (which leaves the process-wide tuning unchanged).
+  BatchedTable modes = batched_table();
+  if (tune_path && tune_parse(tune_path, modes, true) != NBODY_OK) return nullptr;
 
   nbody_plan *p = new nbody_plan();
   p->K = K;
   p->variant = variant;
   p->offsets.assign(offsets_host, offsets_host + K + 1);
-  p->eps.assign(eps_host, eps_host + K);
   p->n_total = offsets_host[K];
 
   // Slot layout: cluster k's sources start at a multiple of kSlotAlign and
@@ -567,7 +634,7 @@ nbody_plan *nbody_plan_create(const int64_t *offsets_host, int32_t K, const doub
   for (int32_t k = 0; k < K; ++k) {
     const int64_t s = p->offsets[k], e = p->offsets[k + 1], nk = e - s;
     if (nk == 0) continue;
-    const int mode = batched_tune(variant, nk);
+    const int mode = modes.mode[variant][size_class(nk)];
     if (nb::batched_mode(mode).smem) p->need_pack = true;
     const int ib = nb::cfg_iblock(nb::batched_mode(mode));
     for (int64_t i = s; i < e; i += ib) {
@@ -608,9 +675,6 @@ nbody_plan *nbody_plan_create(const int64_t *offsets_host, int32_t K, const doub
   if (e == hipSuccess && p->n_slots > 0) e = hipMalloc(&p->d_slot_frame, slot_frame.size() * sizeof(int32_t));
   if (e == hipSuccess && p->n_slots > 0)
     e = hipMemcpy(p->d_slot_frame, slot_frame.data(), slot_frame.size() * sizeof(int32_t), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc(&p->d_eps, static_cast<size_t>(K) * sizeof(double));
-  if (e == hipSuccess)
-    e = hipMemcpy(p->d_eps, p->eps.data(), static_cast<size_t>(K) * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
   for (int m = 0; m < nb::kBatchedModes && e == hipSuccess; ++m) {
     const int32_t cnt = p->seg_end[m] - p->seg_begin[m];
@@ -635,7 +699,6 @@ void nbody_plan_destroy(nbody_plan *p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->capture) (void)hipStreamDestroy(p->capture);
   if (p->d_items) (void)hipFree(p->d_items);
-  if (p->d_eps) (void)hipFree(p->d_eps);
   if (p->d_slot_src) (void)hipFree(p->d_slot_src);
   if (p->d_slot_frame) (void)hipFree(p->d_slot_frame);
   delete p;
@@ -647,45 +710,37 @@ int32_t nbody_plan_variant(const nbody_plan *p) { return p ? p->variant : -1; }
 int64_t nbody_plan_items(const nbody_plan *p) { return p ? p->n_items : -1; }
 double nbody_plan_pairs(const nbody_plan *p) { return p ? p->pairs : -1.0; }
 
-nbody_status nbody_accel_batched(const double *pos, const double *mass, nbody_plan *plan, double G,
-                                 double *acc, double *pot, void *ws, size_t ws_bytes,
-                                 void *stream) {
+nbody_status nbody_accel_batched(const double *pos, const double *mass, const nbody_plan *plan,
+                                 const double *eps_k, double G, int32_t variant, double *acc,
+                                 double *pot, void *ws, size_t ws_bytes, void *stream) {
   g_err.clear();
-  if (!plan) return fail(NBODY_EINVAL, "plan is NULL");
+  nbody_status st = check_batched(plan, variant, eps_k);
+  if (st != NBODY_OK) return st;
   if (!std::isfinite(G)) return fail(NBODY_EINVAL, "G must be finite");
   const int64_t n = plan->n_total;
   if (n == 0) return NBODY_OK;
   if (!pos || !mass || !acc) return fail(NBODY_EINVAL, "pos, mass and acc must be non-NULL");
   const size_t b3 = static_cast<size_t>(n) * 3 * sizeof(double), b1 = static_cast<size_t>(n) * sizeof(double);
+  const size_t bk = static_cast<size_t>(plan->K) * sizeof(double);
   if (overlap(acc, b3, pos, b3) || overlap(acc, b3, mass, b1) || overlap(pot, b1, pos, b3) ||
-      overlap(pot, b1, mass, b1) || overlap(pot, b1, acc, b3))
+      overlap(pot, b1, mass, b1) || overlap(pot, b1, acc, b3) || overlap(acc, b3, eps_k, bk) ||
+      overlap(pot, b1, eps_k, bk))
     return fail(NBODY_EINVAL, "output arrays overlap inputs or each other");
-  nbody_status st = check_ws(ws, ws_bytes, n, plan->variant, plan->K);
+  st = check_ws(ws, ws_bytes, n, plan->variant, plan->K);
   if (st != NBODY_OK) return st;
-  const hipError_t e = enqueue_batched(pos, mass, plan, G, acc, pot, ws, static_cast<hipStream_t>(stream));
+  const hipError_t e = enqueue_batched(pos, mass, plan, eps_k, G, acc, pot, ws, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "nbody_accel_batched launch");
   return NBODY_OK;
 }
 
-nbody_status nbody_step(double *pos, double *vel, double *acc, double *pot, const double *mass,
-                        int64_t n, double eps, double G, double dt, int32_t n_steps,
-                        int32_t variant, nbody_plan *plan, double *diag, void *ws,
-                        size_t ws_bytes, void *stream) {
-  g_err.clear();
+// Checks shared by the KDK entry points: sizes, scalars and overlaps of the
+// state arrays (eps_k, when given, is an input that no output may overlap).
+static nbody_status check_step_args(double *pos, double *vel, double *acc, double *pot, const double *mass,
+                             int64_t n, double dt, int32_t n_steps, double *diag,
+                             const double *eps_k, int32_t K) {
   if (n < 0) return fail(NBODY_EINVAL, "n must be >= 0");
   if (n_steps < 0) return fail(NBODY_EINVAL, "n_steps must be >= 0 (got %d)", n_steps);
-  if (!valid_variant(variant)) return fail(NBODY_ENOTSUP, "unknown variant %d", variant);
   if (!std::isfinite(dt)) return fail(NBODY_EINVAL, "dt must be finite");
-  nbody_status st = plan ? (std::isfinite(G) ? NBODY_OK : fail(NBODY_EINVAL, "G must be finite"))
-                         : check_scalars(eps, G);
-  if (st != NBODY_OK) return st;
-  if (plan) {
-    if (plan->n_total != n)
-      return fail(NBODY_EINVAL, "plan covers %lld particles, n = %lld",
-                  static_cast<long long>(plan->n_total), static_cast<long long>(n));
-    if (plan->variant != variant)
-      return fail(NBODY_EINVAL, "variant %d does not match the plan's %d", variant, plan->variant);
-  }
   if (n == 0 || n_steps == 0) return NBODY_OK;
   if (!pos || !vel || !acc || !mass) return fail(NBODY_EINVAL, "pos, vel, acc and mass must be non-NULL");
   const size_t b3 = static_cast<size_t>(n) * 3 * sizeof(double), b1 = static_cast<size_t>(n) * sizeof(double);
@@ -694,27 +749,72 @@ nbody_status nbody_step(double *pos, double *vel, double *acc, double *pot, cons
       overlap(pot, b1, pos, b3) || overlap(pot, b1, vel, b3) || overlap(pot, b1, acc, b3) ||
       overlap(pot, b1, mass, b1))
     return fail(NBODY_EINVAL, "arrays overlap");
-  if (diag && (overlap(diag, static_cast<size_t>(n_steps) * nb::kDiagLen * sizeof(double), pos, b3) ||
-               overlap(diag, static_cast<size_t>(n_steps) * nb::kDiagLen * sizeof(double), vel, b3) ||
-               overlap(diag, static_cast<size_t>(n_steps) * nb::kDiagLen * sizeof(double), acc, b3)))
+  const size_t db = static_cast<size_t>(n_steps) * nb::kDiagLen * sizeof(double);
+  if (diag && (overlap(diag, db, pos, b3) || overlap(diag, db, vel, b3) || overlap(diag, db, acc, b3) ||
+               overlap(diag, db, pot, b1) || overlap(diag, db, mass, b1)))
     return fail(NBODY_EINVAL, "diag overlaps the state arrays");
-  st = check_ws(ws, ws_bytes, n, variant, plan ? plan->K : 1);
+  if (eps_k) {
+    const size_t bk = static_cast<size_t>(K) * sizeof(double);
+    if (overlap(eps_k, bk, pos, b3) || overlap(eps_k, bk, vel, b3) || overlap(eps_k, bk, acc, b3) ||
+        overlap(eps_k, bk, pot, b1) || (diag && overlap(eps_k, bk, diag, db)))
+      return fail(NBODY_EINVAL, "eps_k overlaps an output array");
+  }
+  return NBODY_OK;
+}
+
+nbody_status nbody_step(double *pos, double *vel, double *acc, double *pot, const double *mass,
+                        int64_t n, double eps, double G, double dt, int32_t n_steps,
+                        int32_t variant, const nbody_plan *plan, double *diag, void *ws,
+                        size_t ws_bytes, void *stream) {
+  g_err.clear();
+  if (plan)
+    return fail(NBODY_EINVAL,
+                "nbody_step steps a single system (plan must be NULL); batched steps take "
+                "per-cluster softenings through nbody_step_batched");
+  if (!valid_variant(variant)) return fail(NBODY_ENOTSUP, "unknown variant %d", variant);
+  nbody_status st = check_scalars(eps, G);
+  if (st != NBODY_OK) return st;
+  st = check_step_args(pos, vel, acc, pot, mass, n, dt, n_steps, diag, nullptr, 0);
+  if (st != NBODY_OK) return st;
+  if (n == 0 || n_steps == 0) return NBODY_OK;
+  st = check_ws(ws, ws_bytes, n, variant, 1);
   if (st != NBODY_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const WsLayout L = ws_layout(n, variant, plan ? plan->K : 1);
+  const WsLayout L = ws_layout(n, variant, 1);
   hipError_t e = hipSuccess;
   if (diag) e = nb::launch_fill_int(at<int>(ws, L.ctr), 1, 0, s);
-  if (e != hipSuccess) return hip_fail(e, "nbody_step");
+  for (int32_t k = 0; k < n_steps && e == hipSuccess; ++k)
+    e = enqueue_step(pos, vel, acc, pot, mass, n, eps, G, dt, variant, nullptr, nullptr, diag, ws, s);
+  if (e != hipSuccess) return hip_fail(e, "nbody_step launch");
+  return NBODY_OK;
+}
 
-  if (!plan) {
-    for (int32_t k = 0; k < n_steps && e == hipSuccess; ++k)
-      e = enqueue_step(pos, vel, acc, pot, mass, n, eps, G, dt, variant, nullptr, diag, ws, s);
-    if (e != hipSuccess) return hip_fail(e, "nbody_step launch");
-    return NBODY_OK;
-  }
+nbody_status nbody_step_batched(double *pos, double *vel, double *acc, double *pot,
+                                const double *mass, int64_t n, const nbody_plan *plan,
+                                const double *eps_k, double G, double dt, int32_t n_steps,
+                                int32_t variant, double *diag, void *ws, size_t ws_bytes,
+                                void *stream) {
+  g_err.clear();
+  nbody_status st = check_batched(plan, variant, eps_k);
+  if (st != NBODY_OK) return st;
+  if (!std::isfinite(G)) return fail(NBODY_EINVAL, "G must be finite");
+  if (n >= 0 && plan->n_total != n)
+    return fail(NBODY_EINVAL, "plan covers %lld particles, n = %lld",
+                static_cast<long long>(plan->n_total), static_cast<long long>(n));
+  st = check_step_args(pos, vel, acc, pot, mass, n, dt, n_steps, diag, eps_k, plan->K);
+  if (st != NBODY_OK) return st;
+  if (n == 0 || n_steps == 0) return NBODY_OK;
+  st = check_ws(ws, ws_bytes, n, variant, plan->K);
+  if (st != NBODY_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const WsLayout L = ws_layout(n, variant, plan->K);
+  hipError_t e = hipSuccess;
+  if (diag) e = nb::launch_fill_int(at<int>(ws, L.ctr), 1, 0, s);
+  if (e != hipSuccess) return hip_fail(e, "nbody_step_batched");
 
-  // Batched: capture one step as a graph (once per argument set), replay it.
-  const void *key[9] = {pos, vel, acc, pot, mass, diag, ws, nullptr, nullptr};
+  // Capture one step as a graph (once per argument set), then replay it.
+  // eps_k is read from device memory at every replay.
+  const void *key[10] = {pos, vel, acc, pot, mass, diag, ws, eps_k, nullptr, nullptr};
   const bool same = plan->exec && std::memcmp(key, plan->key, sizeof(key)) == 0 &&
                     plan->key_g == G && plan->key_dt == dt;
   if (!same) {
@@ -725,7 +825,7 @@ nbody_status nbody_step(double *pos, double *vel, double *acc, double *pot, cons
     hipGraph_t graph = nullptr;
     e = hipStreamBeginCapture(plan->capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    const hipError_t le = enqueue_step(pos, vel, acc, pot, mass, n, 0.0, G, dt, variant, plan,
+    const hipError_t le = enqueue_step(pos, vel, acc, pot, mass, n, 0.0, G, dt, variant, plan, eps_k,
                                        diag, ws, plan->capture);
     e = hipStreamEndCapture(plan->capture, &graph);
     if (le != hipSuccess) {

@@ -179,4 +179,18 @@ hipError_t launch_diag_final(const double *partial, double *diag, int *step_ctr,
                              hipStream_t stream);
 hipError_t launch_fill_int(int *p, int n, int value, hipStream_t stream);
 
+// Single-system force evaluation behind nbody_accel (abi.cpp), with the grid
+// j-split capped at split_cap (the workspace then needs accel_ws_bytes(n,
+// variant, split_cap) bytes). Returns an nbody_status and sets the thread's
+// last-error text.
+int32_t accel_entry(const double *pos, const double *mass, int64_t n, double eps, double G,
+                    int32_t variant, double *acc, double *pot, void *ws, size_t ws_bytes,
+                    int split_cap, void *stream);
+// Host-only checks of nbody_accel's arguments (everything but the workspace).
+int32_t check_accel_args(const double *pos, const double *mass, int64_t n, double eps, double G,
+                         int32_t variant, const double *acc, const double *pot);
+size_t accel_ws_bytes(int64_t n, int32_t variant, int split_cap);
+int accel_tuned_split(int32_t variant, int64_t n);  // the split nbody_accel would use
+int32_t set_error(int32_t status, const char *msg);  // records msg, returns status
+
 }  // namespace nb

@@ -7,7 +7,8 @@ streams. The library is loaded on first use; if it is missing, every call
 raises (there is no fallback).
 
 Names follow the C ABI of ``include/nbody.h``: ``accel`` (nbody_accel),
-``step`` (nbody_step), ``Plan`` (nbody_plan_create / nbody_accel_batched).
+``step`` (nbody_step), ``Plan`` (nbody_plan_create; ``Plan.accel`` is
+nbody_accel_batched), ``step_batched`` (nbody_step_batched).
 """
 from __future__ import annotations
 
@@ -54,12 +55,15 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
             "nbody_last_error": (ctypes.c_char_p, []),
             "nbody_version": (ctypes.c_char_p, []),
             "nbody_accel": (i32, [c_dp, c_dp, i64, dbl, dbl, i32, c_dp, c_dp, c_dp, sz, c_dp]),
+            "nbody_accel_noalloc": (i32, [c_dp, c_dp, i64, dbl, dbl, i32, c_dp, c_dp, c_dp]),
             "nbody_step": (i32, [c_dp, c_dp, c_dp, c_dp, c_dp, i64, dbl, dbl, dbl, i32, i32, c_dp,
                                  c_dp, c_dp, sz, c_dp]),
-            "nbody_plan_create": (c_dp, [ctypes.POINTER(i64), i32, ctypes.POINTER(dbl), i32,
-                                         ctypes.c_char_p]),
+            "nbody_step_batched": (i32, [c_dp, c_dp, c_dp, c_dp, c_dp, i64, c_dp, c_dp, dbl, dbl, i32,
+                                         i32, c_dp, c_dp, sz, c_dp]),
+            "nbody_plan_create": (c_dp, [ctypes.POINTER(i64), i32, i32, ctypes.c_char_p]),
             "nbody_plan_destroy": (None, [c_dp]),
-            "nbody_accel_batched": (i32, [c_dp, c_dp, c_dp, dbl, c_dp, c_dp, c_dp, sz, c_dp]),
+            "nbody_accel_batched": (i32, [c_dp, c_dp, c_dp, c_dp, dbl, i32, c_dp, c_dp, c_dp, sz,
+                                          c_dp]),
             "nbody_plan_total": (i64, [c_dp]),
             "nbody_plan_clusters": (i32, [c_dp]),
             "nbody_plan_variant": (i32, [c_dp]),
@@ -181,10 +185,45 @@ def accel(pos: torch.Tensor, mass: torch.Tensor, eps: float, G: float = 1.0, var
     return acc, pot
 
 
-def step(pos, vel, acc, mass, eps: float, G: float, dt: float, n_steps: int, variant=None,
-         plan: "Plan | None" = None, diag: bool | torch.Tensor = True,
-         pot: torch.Tensor | None = None, ws: torch.Tensor | None = None):
-    """``n_steps`` kick-drift-kick steps in place on (pos, vel, acc): nbody_step.
+def _diag(diag, n_steps, device):
+    if diag is True:
+        diag = torch.empty((max(int(n_steps), 0), DIAG_LEN), dtype=torch.float64, device=device)
+    elif diag is False:
+        diag = None
+    if diag is not None and (diag.dtype != torch.float64 or diag.shape != (n_steps, DIAG_LEN)
+                             or not diag.is_contiguous()):
+        raise ValueError("diag must be a contiguous float64 tensor of shape (n_steps, 16)")
+    return diag
+
+
+def accel_noalloc(pos: torch.Tensor, mass: torch.Tensor, eps: float, G: float = 1.0, variant="plain",
+                  acc: torch.Tensor | None = None, pot: torch.Tensor | bool | None = True):
+    """nbody_accel without a workspace (the library's static scratch):
+    nbody_accel_noalloc. Returns ``(acc, pot)``. Pass preallocated ``acc``
+    and ``pot`` to keep the call free of allocations."""
+    lib = load()
+    _vec3(pos, "pos")
+    n = pos.shape[0]
+    _vec1(mass, "mass", n)
+    acc = torch.empty_like(pos) if acc is None else _vec3(acc, "acc", n)
+    if pot is True:
+        pot = torch.empty_like(mass)
+    elif pot is False:
+        pot = None
+    if pot is not None:
+        _vec1(pot, "pot", n)
+    st = lib.nbody_accel_noalloc(pos.data_ptr(), mass.data_ptr(), n, float(eps), float(G), _variant(variant),
+                                 acc.data_ptr(), pot.data_ptr() if pot is not None else None,
+                                 _stream_handle(pos.device))
+    _check(st)
+    return acc, pot
+
+
+def step(pos, vel, acc, mass, eps: float, G: float, dt: float, n_steps: int, variant="plain",
+         diag: bool | torch.Tensor = True, pot: torch.Tensor | None = None,
+         ws: torch.Tensor | None = None):
+    """``n_steps`` kick-drift-kick steps of one system in place on (pos, vel,
+    acc): nbody_step.
 
     ``acc`` must hold the accelerations at ``pos`` on entry. Returns the
     diagnostics tensor of shape (n_steps, 16) (or None when ``diag=False``).
@@ -197,25 +236,43 @@ def step(pos, vel, acc, mass, eps: float, G: float, dt: float, n_steps: int, var
     _vec1(mass, "mass", n)
     if pot is not None:
         _vec1(pot, "pot", n)
-    if variant is None:
-        variant = plan.variant if plan is not None else PLAIN
     v = _variant(variant)
-    if diag is True:
-        diag = torch.empty((max(int(n_steps), 0), DIAG_LEN), dtype=torch.float64, device=pos.device)
-    elif diag is False:
-        diag = None
-    if diag is not None and (diag.dtype != torch.float64 or diag.shape != (n_steps, DIAG_LEN)
-                             or not diag.is_contiguous()):
-        raise ValueError("diag must be a contiguous float64 tensor of shape (n_steps, 16)")
-    k = plan.K if plan is not None else 1
+    diag = _diag(diag, n_steps, pos.device)
     if ws is None:
-        ws = workspace(n, k, v, pos.device)
+        ws = workspace(n, 1, v, pos.device)
     st = lib.nbody_step(pos.data_ptr(), vel.data_ptr(), acc.data_ptr(),
                         pot.data_ptr() if pot is not None else None, mass.data_ptr(), n,
-                        float(eps), float(G), float(dt), int(n_steps), v,
-                        plan.handle if plan is not None else None,
+                        float(eps), float(G), float(dt), int(n_steps), v, None,
                         diag.data_ptr() if (diag is not None and n_steps > 0) else None,
                         ws.data_ptr(), ws.numel(), _stream_handle(pos.device))
+    _check(st)
+    return diag
+
+
+def step_batched(pos, vel, acc, mass, plan: "Plan", eps_k: torch.Tensor, G: float, dt: float,
+                 n_steps: int, diag: bool | torch.Tensor = True, pot: torch.Tensor | None = None,
+                 ws: torch.Tensor | None = None):
+    """``n_steps`` kick-drift-kick steps of every cluster of ``plan`` in place,
+    cluster k softened by ``eps_k[k]`` (a float64 CUDA tensor of shape (K,)):
+    nbody_step_batched. ``acc`` must hold the accelerations at ``pos``."""
+    lib = load()
+    n = plan.n_total
+    _vec3(pos, "pos", n)
+    _vec3(vel, "vel", n)
+    _vec3(acc, "acc", n)
+    _vec1(mass, "mass", n)
+    _vec1(eps_k, "eps_k", plan.K)
+    if pot is not None:
+        _vec1(pot, "pot", n)
+    diag = _diag(diag, n_steps, pos.device)
+    if ws is None:
+        ws = workspace(n, plan.K, plan.variant, pos.device)
+    st = lib.nbody_step_batched(pos.data_ptr(), vel.data_ptr(), acc.data_ptr(),
+                                pot.data_ptr() if pot is not None else None, mass.data_ptr(), n,
+                                plan.handle, eps_k.data_ptr(), float(G), float(dt), int(n_steps),
+                                plan.variant,
+                                diag.data_ptr() if (diag is not None and n_steps > 0) else None,
+                                ws.data_ptr(), ws.numel(), _stream_handle(pos.device))
     _check(st)
     return diag
 
@@ -260,13 +317,7 @@ def step_hermite(pos, vel, acc, jerk, mass, eps: float, G: float, dt: float, n_s
     if pot is not None:
         _vec1(pot, "pot", n)
     v = _variant(variant)
-    if diag is True:
-        diag = torch.empty((max(int(n_steps), 0), DIAG_LEN), dtype=torch.float64, device=pos.device)
-    elif diag is False:
-        diag = None
-    if diag is not None and (diag.dtype != torch.float64 or diag.shape != (n_steps, DIAG_LEN)
-                             or not diag.is_contiguous()):
-        raise ValueError("diag must be a contiguous float64 tensor of shape (n_steps, 16)")
+    diag = _diag(diag, n_steps, pos.device)
     if ws is None:
         ws = workspace(n, 1, v, pos.device, need=int(lib.nbody_workspace_bytes_jerk(n, v)))
     st = lib.nbody_step_hermite(pos.data_ptr(), vel.data_ptr(), acc.data_ptr(), jerk.data_ptr(),
@@ -279,23 +330,25 @@ def step_hermite(pos, vel, acc, jerk, mass, eps: float, G: float, dt: float, n_s
 
 
 class Plan:
-    """A batched plan over K independent clusters (nbody_plan_create)."""
+    """A batched plan over independent clusters (nbody_plan_create).
 
-    def __init__(self, offsets, eps, variant="comp", tune_path: str | None = None):
+    ``offsets`` has K + 1 entries: cluster k owns particles
+    [offsets[k], offsets[k + 1]). The per-cluster softenings are passed to
+    every call (``accel``, ``step_batched``), not stored in the plan.
+    """
+
+    def __init__(self, offsets, variant="comp", tune_path: str | None = None):
         import numpy as np
 
         lib = load()
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
-        ep = np.ascontiguousarray(np.asarray(eps, dtype=np.float64))
-        if off.ndim != 1 or ep.ndim != 1 or off.shape[0] != ep.shape[0] + 1:
-            raise ValueError("offsets must have K + 1 entries and eps K entries")
-        self.K = int(ep.shape[0])
+        if off.ndim != 1 or off.shape[0] < 2:
+            raise ValueError("offsets must have K + 1 >= 2 entries")
+        self.K = int(off.shape[0] - 1)
         self.variant = _variant(variant)
         self.offsets = off
-        self.eps = ep
         h = lib.nbody_plan_create(off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), self.K,
-                                  ep.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.variant,
-                                  tune_path.encode() if tune_path else None)
+                                  self.variant, tune_path.encode() if tune_path else None)
         if not h:
             raise NbodyError(EINVAL, last_error())
         self.handle = ctypes.c_void_p(h)
@@ -314,12 +367,15 @@ class Plan:
         except Exception:
             pass
 
-    def accel(self, pos, mass, G: float = 1.0, acc=None, pot=True, ws=None):
-        """Accelerations of every cluster from its own members: nbody_accel_batched."""
+    def accel(self, pos, mass, eps_k, G: float = 1.0, acc=None, pot=True, ws=None):
+        """Accelerations of every cluster from its own members, cluster k
+        softened by ``eps_k[k]`` (float64 CUDA tensor of shape (K,)):
+        nbody_accel_batched."""
         lib = load()
         n = self.n_total
         _vec3(pos, "pos", n)
         _vec1(mass, "mass", n)
+        _vec1(eps_k, "eps_k", self.K)
         if acc is None:
             acc = torch.empty_like(pos)
         _vec3(acc, "acc", n)
@@ -331,8 +387,9 @@ class Plan:
             _vec1(pot, "pot", n)
         if ws is None:
             ws = workspace(n, self.K, self.variant, pos.device)
-        st = lib.nbody_accel_batched(pos.data_ptr(), mass.data_ptr(), self.handle, float(G),
-                                     acc.data_ptr(), pot.data_ptr() if pot is not None else None,
+        st = lib.nbody_accel_batched(pos.data_ptr(), mass.data_ptr(), self.handle, eps_k.data_ptr(),
+                                     float(G), self.variant, acc.data_ptr(),
+                                     pot.data_ptr() if pot is not None else None,
                                      ws.data_ptr(), ws.numel(), _stream_handle(pos.device))
         _check(st)
         return acc, pot

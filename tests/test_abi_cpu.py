@@ -118,38 +118,73 @@ def test_step_zero_steps_is_noop(lib):
     assert _step(lib, n_steps=0) == nbody.OK
 
 
-def _plan(lib, offsets, eps, variant=1):
+def _plan(lib, offsets, variant=1, tune_path=None):
     import numpy as np
     off = np.asarray(offsets, dtype=np.int64)
-    ep = np.asarray(eps, dtype=np.float64)
-    return lib.nbody_plan_create(off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(ep),
-                                 ep.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), variant, None)
+    return lib.nbody_plan_create(off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(off) - 1,
+                                 variant, tune_path)
 
 
-@pytest.mark.parametrize("offsets,eps,variant", [
-    ([1, 5], [0.1], 1),            # offsets[0] != 0
-    ([0, 5, 3], [0.1, 0.1], 1),    # decreasing
-    ([0, 5], [-0.1], 1),           # negative eps
-    ([0, 5], [math.nan], 1),       # non-finite eps
-    ([0, 5], [0.1], 9),            # unknown variant
-    ([0, 2 ** 31], [0.1], 1),      # too large for a batched plan
+@pytest.mark.parametrize("offsets,variant", [
+    ([1, 5], 1),            # offsets[0] != 0
+    ([0, 5, 3], 1),         # decreasing
+    ([0, 5], 9),            # unknown variant
+    ([0, 2 ** 31], 1),      # too large for a batched plan
+    ([0, 2 ** 31 - 20], 0),  # too large once every cluster is padded to 16 slots
 ])
-def test_plan_create_rejects(lib, offsets, eps, variant):
-    assert not _plan(lib, offsets, eps, variant)
+def test_plan_create_rejects(lib, offsets, variant):
+    assert not _plan(lib, offsets, variant)
     assert lib.nbody_last_error().decode() != ""
 
 
-def test_plan_create_rejects_k0(lib):
+def test_plan_create_rejects_k0_and_null(lib):
     import numpy as np
     off = np.zeros(1, dtype=np.int64)
-    ep = np.zeros(1)
-    assert not lib.nbody_plan_create(off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 0,
-                                     ep.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1, None)
+    assert not lib.nbody_plan_create(off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 0, 1, None)
+    assert not lib.nbody_plan_create(None, 3, 1, None)
+    assert "offsets" in lib.nbody_last_error().decode()
 
 
-def test_batched_rejects_null_plan(lib):
-    st = lib.nbody_accel_batched(FAKE, FAKE2, None, 1.0, FAKE3, None, FAKE, 1 << 20, None)
-    assert st == nbody.EINVAL
+def test_plan_create_rejects_a_bad_tuning_file(lib, tmp_path):
+    bad = tmp_path / "bad.txt"
+    bad.write_text("batched 1 12 99\n")
+    assert not _plan(lib, [0, 5, 9], 1, str(bad).encode())
+    assert "bad batched entry" in lib.nbody_last_error().decode()
+    assert not _plan(lib, [0, 5, 9], 1, str(tmp_path / "missing.txt").encode())
+
+
+def test_plan_tuning_file_leaves_the_process_table_alone(lib, tmp_path):
+    """A plan's tuning file must not retune later single-system calls: its
+    single and jerk lines are checked but only its batched lines apply, and
+    only to that plan. (Plan creation itself needs a GPU for its device
+    arrays, so on the CPU the call fails after the file is read.)"""
+    before = (nbody.tune_get("plain", 1 << 20), nbody.tune_get("comp", 5000),
+              nbody.tune_jerk_get("comp", 1 << 16))
+    f = tmp_path / "plan.txt"
+    f.write_text("single 0 20 2 4\nsingle 1 12 3 2\njerk 1 16 4 2\nbatched 1 11 1\n")
+    h = _plan(lib, [0, 5, 9], 1, str(f).encode())
+    if h:
+        lib.nbody_plan_destroy(h)
+    after = (nbody.tune_get("plain", 1 << 20), nbody.tune_get("comp", 5000),
+             nbody.tune_jerk_get("comp", 1 << 16))
+    assert after == before
+
+
+def test_batched_calls_reject_null_plan(lib):
+    eps = ctypes.c_void_p(0x5000000)
+    st = lib.nbody_accel_batched(FAKE, FAKE2, None, eps, 1.0, 1, FAKE3, None, FAKE, 1 << 20, None)
+    assert st == nbody.EINVAL and "plan" in lib.nbody_last_error().decode()
+    st = lib.nbody_step_batched(FAKE, ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000), None,
+                                ctypes.c_void_p(0x400000), 64, None, eps, 1.0, 0.01, 3, 1, None,
+                                ctypes.c_void_p(0x7000000), 1 << 20, None)
+    assert st == nbody.EINVAL and "plan" in lib.nbody_last_error().decode()
+
+
+def test_step_rejects_a_plan(lib):
+    """nbody_step steps one system; a plan (whose clusters need per-cluster
+    softenings) is refused before it is touched."""
+    assert _step(lib, plan=ctypes.c_void_p(0x123400)) == nbody.EINVAL
+    assert "nbody_step_batched" in lib.nbody_last_error().decode()
 
 
 def test_tuning_table(lib, tmp_path):
@@ -276,3 +311,21 @@ def test_jerk_shapes_and_forcing(lib, tmp_path):
     nbody.tune_jerk_set("comp", 2, 4)
     nbody.tune_reset()
     assert nbody.tune_jerk_get("comp", n) != (2, 4) and nbody.tune_jerk_get("comp", n) != (4, 2)
+
+
+def test_noalloc_validates_before_touching_a_device(lib):
+    """nbody_accel_noalloc checks its arguments and its size limit on the
+    host, before it looks up its scratch on a device."""
+    def call(n=100, eps=0.01, variant=0, pos=FAKE, acc=FAKE3):
+        return lib.nbody_accel_noalloc(pos, FAKE2, n, eps, 1.0, variant, acc, None, None)
+    assert call(n=-1) == nbody.EINVAL
+    assert call(variant=3) == nbody.ENOTSUP
+    assert call(eps=math.nan) == nbody.EINVAL
+    assert call(pos=None) == nbody.EINVAL
+    assert call(acc=FAKE) == nbody.EINVAL
+    assert call(n=0, pos=None, acc=None) == nbody.OK
+    # the static scratch holds at most 1,676,064 (plain) / 536,480 (compensated) particles
+    assert call(n=1676065, variant=0, acc=ctypes.c_void_p(0x40000000)) == nbody.EINVAL
+    assert "scratch" in lib.nbody_last_error().decode()
+    assert call(n=536481, variant=1, acc=ctypes.c_void_p(0x40000000)) == nbody.EINVAL
+    assert "scratch" in lib.nbody_last_error().decode()

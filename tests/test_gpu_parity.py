@@ -307,11 +307,11 @@ def _batched_ref(ens):
 def test_batched_matches_per_cluster_oracle(variant):
     ens = _small_ensemble()
     ref_a, ref_p = _batched_ref(ens)
-    plan = nbody.Plan(ens.offsets, ens.eps, variant)
+    plan = nbody.Plan(ens.offsets, variant)
     assert plan.n_total == len(ens.mass)
     assert plan.pairs == float(np.sum(ens.sizes.astype(np.float64) ** 2))
-    a1, p1 = plan.accel(T(ens.pos), T(ens.mass))
-    a2, p2 = plan.accel(T(ens.pos), T(ens.mass))
+    a1, p1 = plan.accel(T(ens.pos), T(ens.mass), T(ens.eps))
+    a2, p2 = plan.accel(T(ens.pos), T(ens.mass), T(ens.eps))
     torch.cuda.synchronize()
     a1, p1, a2, p2 = (x.cpu().numpy() for x in (a1, p1, a2, p2))
     assert np.array_equal(a1, a2) and np.array_equal(p1, p2)
@@ -333,9 +333,9 @@ def test_batched_every_mode(variant, tmp_path):
         for mode in range(len(nbody.batched_modes())):
             path = tmp_path / f"mode{mode}.txt"
             path.write_text("".join(f"batched {v} {c} {mode}\n" for c in range(48)))
-            plan = nbody.Plan(ens.offsets, ens.eps, variant, tune_path=str(path))
-            a1, p1 = plan.accel(T(ens.pos), T(ens.mass))
-            a2, p2 = plan.accel(T(ens.pos), T(ens.mass))
+            plan = nbody.Plan(ens.offsets, variant, tune_path=str(path))
+            a1, p1 = plan.accel(T(ens.pos), T(ens.mass), T(ens.eps))
+            a2, p2 = plan.accel(T(ens.pos), T(ens.mass), T(ens.eps))
             torch.cuda.synchronize()
             a1, p1, a2, p2 = (x.cpu().numpy() for x in (a1, p1, a2, p2))
             assert np.array_equal(a1, a2) and np.array_equal(p1, p2), mode
@@ -354,10 +354,104 @@ def test_batched_leakage():
     ref_a, _ = _batched_ref(ens)
     whole_a, _ = orc.accel_pot(ens.pos, ens.mass, float(ens.eps.min()))
     assert orc.rel_rms(whole_a, ref_a) > 0.1
-    plan = nbody.Plan(ens.offsets, ens.eps, "comp")
-    a, _ = plan.accel(T(ens.pos), T(ens.mass))
+    plan = nbody.Plan(ens.offsets, "comp")
+    a, _ = plan.accel(T(ens.pos), T(ens.mass), T(ens.eps))
     torch.cuda.synchronize()
     assert orc.rel_rms(a.cpu().numpy(), ref_a) < RMS_TOL
+
+
+def test_batched_eps_k_per_call():
+    """The softenings are an argument of every batched call: one plan, two
+    eps_k arrays (the second scales cluster k's softening by a different
+    factor per cluster, one cluster unsoftened), each result equal per
+    cluster to the oracle with that cluster's own softening."""
+    ens = _small_ensemble(k=9, seed=23)
+    plan = nbody.Plan(ens.offsets, "comp")
+    tp, tm = T(ens.pos), T(ens.mass)
+    eps_b = ens.eps * np.linspace(0.5, 4.0, len(ens.eps))
+    eps_b[3] = 0.0
+    results = []
+    for eps in (ens.eps, eps_b):
+        a, p = plan.accel(tp, tm, T(eps))
+        torch.cuda.synchronize()
+        a, p = a.cpu().numpy(), p.cpu().numpy()
+        for c in range(len(ens.sizes)):
+            s, e = ens.offsets[c], ens.offsets[c + 1]
+            ra, rp = orc.accel_pot(ens.pos[s:e], ens.mass[s:e], float(eps[c]))
+            check(a[s:e], p[s:e], ra, rp, what=("eps_k", c, eps[c]))
+        results.append(a)
+    # the softening really changed every cluster's result
+    for c in range(len(ens.sizes)):
+        s, e = ens.offsets[c], ens.offsets[c + 1]
+        assert orc.rel_rms(results[1][s:e], results[0][s:e]) > 1e-4, c
+    plan.close()
+
+
+def test_batched_call_validation_with_a_plan():
+    """Host-side checks that need a real plan: the variant must be the
+    plan's, eps_k must be present, aligned and apart from the outputs; a
+    rejected call leaves its outputs untouched."""
+    lib = nbody.load()
+    ens = _small_ensemble(k=4, seed=31)
+    plan = nbody.Plan(ens.offsets, "comp")
+    tp, tm, te = T(ens.pos), T(ens.mass), T(ens.eps)
+    acc = torch.full_like(tp, 7.0)
+    ws = nbody.workspace(plan.n_total, plan.K, "comp", DEV)
+    n = plan.n_total
+
+    def call(eps_ptr, variant=1, acc_ptr=None):
+        return lib.nbody_accel_batched(tp.data_ptr(), tm.data_ptr(), plan.handle, eps_ptr, 1.0, variant,
+                                       acc.data_ptr() if acc_ptr is None else acc_ptr, None,
+                                       ws.data_ptr(), ws.numel(), nbody._stream_handle(tp.device))
+    assert call(te.data_ptr(), variant=0) == nbody.EINVAL
+    assert "variant" in nbody.last_error()
+    assert call(te.data_ptr(), variant=5) == nbody.ENOTSUP
+    assert call(None) == nbody.EINVAL
+    assert call(te.data_ptr() + 4) == nbody.EINVAL
+    assert call(acc.data_ptr() + 8) == nbody.EINVAL          # eps_k inside acc
+    torch.cuda.synchronize()
+    assert torch.all(acc == 7.0)
+    vel = torch.zeros_like(tp)
+    st = lib.nbody_step_batched(tp.data_ptr(), vel.data_ptr(), acc.data_ptr(), None, tm.data_ptr(), n,
+                                plan.handle, vel.data_ptr(), 1.0, 0.01, 1, 1, None, ws.data_ptr(),
+                                ws.numel(), nbody._stream_handle(tp.device))
+    assert st == nbody.EINVAL and "eps_k" in nbody.last_error()  # eps_k overlaps vel
+    st = lib.nbody_step_batched(tp.data_ptr(), vel.data_ptr(), acc.data_ptr(), None, tm.data_ptr(), n + 1,
+                                plan.handle, te.data_ptr(), 1.0, 0.01, 1, 1, None, ws.data_ptr(),
+                                ws.numel(), nbody._stream_handle(tp.device))
+    assert st == nbody.EINVAL and "plan covers" in nbody.last_error()
+    st = lib.nbody_step(tp.data_ptr(), vel.data_ptr(), acc.data_ptr(), None, tm.data_ptr(), n, 0.01, 1.0,
+                        0.01, 1, 1, plan.handle, None, ws.data_ptr(), ws.numel(), nbody._stream_handle(tp.device))
+    assert st == nbody.EINVAL and "nbody_step_batched" in nbody.last_error()
+    torch.cuda.synchronize()
+    assert torch.all(acc == 7.0)
+    plan.close()
+
+
+def test_plan_tuning_file_is_plan_local(tmp_path):
+    """A plan created with a tuning file takes its batched modes from it and
+    leaves the process-wide tuning (single-system and jerk tables) alone."""
+    before = (nbody.tune_get("plain", 1 << 20), nbody.tune_get("comp", 5000), nbody.tune_jerk_get("comp", 1 << 16))
+    ens = _small_ensemble(k=6, seed=41)
+    ref_a, ref_p = _batched_ref(ens)
+    f = tmp_path / "plan.txt"
+    f.write_text("single 0 20 2 4\nsingle 1 12 3 2\njerk 1 16 4 2\n"
+                 + "".join(f"batched 1 {c} 0\n" for c in range(48)))
+    plan = nbody.Plan(ens.offsets, "comp", tune_path=str(f))
+    assert (nbody.tune_get("plain", 1 << 20), nbody.tune_get("comp", 5000),
+            nbody.tune_jerk_get("comp", 1 << 16)) == before
+    a, p = plan.accel(T(ens.pos), T(ens.mass), T(ens.eps))
+    default = nbody.Plan(ens.offsets, "comp")
+    a2, _ = default.accel(T(ens.pos), T(ens.mass), T(ens.eps))
+    torch.cuda.synchronize()
+    a, p, a2 = a.cpu().numpy(), p.cpu().numpy(), a2.cpu().numpy()
+    for c in range(len(ens.sizes)):
+        s, e = ens.offsets[c], ens.offsets[c + 1]
+        check(a[s:e], p[s:e], ref_a[s:e], ref_p[s:e], what=("plan-local mode 0", c))
+    # mode 0 (LDS tiles) and the default modes sum in different orders
+    assert not np.array_equal(a, a2)
+    plan.close()
+    default.close()
 
 
 def test_batched_empty_and_single_clusters():
@@ -366,8 +460,8 @@ def test_batched_empty_and_single_clusters():
     rng = np.random.default_rng(4)
     pos = rng.normal(size=(301, 3))
     mass = rng.uniform(0.1, 1.0, size=301)
-    plan = nbody.Plan(offsets, eps, "comp")
-    a, p = plan.accel(T(pos), T(mass))
+    plan = nbody.Plan(offsets, "comp")
+    a, p = plan.accel(T(pos), T(mass), T(eps))
     torch.cuda.synchronize()
     a, p = a.cpu().numpy(), p.cpu().numpy()
     assert np.all(a[0] == 0) and np.all(a[300] == 0) and p[0] == 0 and p[300] == 0
@@ -382,14 +476,15 @@ def test_batched_graph_steps(variant):
     runs, and a split run equals a straight one."""
     ens = _small_ensemble(k=12, seed=13)
     dt, steps = 1.0 / 256, 6
-    plan = nbody.Plan(ens.offsets, ens.eps, variant)
+    plan = nbody.Plan(ens.offsets, variant)
+    te = T(ens.eps)
     outs = []
     for split in ((steps,), (2, 4)):
         tp, tv, tm = T(ens.pos), T(ens.vel), T(ens.mass)
-        acc, _ = plan.accel(tp, tm)
+        acc, _ = plan.accel(tp, tm, te)
         diags = []
         for k in split:
-            diags.append(nbody.step(tp, tv, acc, tm, 0.0, 1.0, dt, k, plan=plan).cpu().numpy())
+            diags.append(nbody.step_batched(tp, tv, acc, tm, plan, te, 1.0, dt, k).cpu().numpy())
         torch.cuda.synchronize()
         outs.append((tp.cpu().numpy(), tv.cpu().numpy(), acc.cpu().numpy(), np.concatenate(diags)))
     for x, y in zip(outs[0][:3], outs[1][:3]):
