@@ -23,7 +23,9 @@ FAKE3 = ctypes.c_void_p(0x1100000)
 
 @pytest.fixture(scope="module")
 def lib():
-    return nbody.load()
+    # NBODY_LIB_UNDER_TEST: another build of the same library (the
+    # sanitizer-instrumented one of tests/test_abi_asan_cpu.py)
+    return nbody.load(os.environ.get("NBODY_LIB_UNDER_TEST", nbody.LIB_PATH))
 
 
 def declared_functions():

@@ -127,18 +127,37 @@ def test_kroupa_1m_ten_steps():
     report_drift("kroupa_1m", "comp", r)
 
 
-def _per_cluster(ens, pos, acc, pot, what):
-    worst = np.zeros(3)
+def _per_cluster(ens, pos, acc, pot, what, variant):
+    """Every cluster against its own oracle. The compensated form meets the
+    metric's tolerances and the paper's per-component criterion against the
+    exact FP64 inputs. The plain form takes its inputs in FP32, and rounding
+    the absolute coordinates alone (the oracle evaluated exactly on the
+    rounded inputs) misses both on a few of this ensemble's clusters: rel-RMS
+    up to 5.7e-5 (12 of 512 clusters above 1e-5) and the paper's metric up to
+    2.5e-3 (10 above 5e-4), on clusters of 4,000-8,000 particles softened by
+    4/N_k. So the plain kernel is held to the metric's tolerances against the
+    oracle on the rounded inputs, and against the exact ones to that
+    rounding's own error plus the tolerance."""
+    worst = np.zeros(4)
     for c in range(len(ens.sizes)):
         s, e = int(ens.offsets[c]), int(ens.offsets[c + 1])
-        ra, rp = ocpu.accel_pot(pos[s:e], ens.mass[s:e], float(ens.eps[c]))
+        x, m = pos[s:e], ens.mass[s:e]
+        ra, rp = ocpu.accel_pot(x, m, float(ens.eps[c]))
         a, p = acc[s:e], pot[s:e]
+        exact = orc.rel_rms(a, ra)
+        if variant == "plain":
+            x32 = x.astype(np.float32).astype(np.float64)
+            m32 = m.astype(np.float32).astype(np.float64)
+            rra, rrp = ocpu.accel_pot(x32, m32, float(ens.eps[c]))
+            assert exact <= orc.rel_rms(rra, ra) + 1e-5, (what, c, exact, orc.rel_rms(rra, ra))
+            ra, rp = rra, rrp
+        else:
+            assert orc.paper_metric(a, ra) <= 5e-4, (what, c)
         e1, e2, e3 = orc.rel_rms(a, ra), orc.max_rel(a, ra), orc.rel_rms(p, rp)
         assert e1 <= 1e-5 and e2 <= 1e-4 and e3 <= 1e-5, (what, c, e - s, e1, e2, e3)
-        assert orc.paper_metric(a, ra) <= 5e-4, (what, c)
-        worst = np.maximum(worst, (e1, e2, e3))
+        worst = np.maximum(worst, (e1, e2, e3, exact))
     print(f"ensemble_512 {what}: worst cluster acc rel-rms {worst[0]:.3e} max-rel {worst[1]:.3e} "
-          f"pot rel-rms {worst[2]:.3e}", flush=True)
+          f"pot rel-rms {worst[2]:.3e}; against exact inputs acc rel-rms {worst[3]:.3e}", flush=True)
 
 
 @pytest.mark.parametrize("variant", ["comp", "plain"])
@@ -154,11 +173,12 @@ def test_ensemble_512_hundred_graph_steps(variant):
     pot = torch.empty_like(tm)
     acc, _ = plan.accel(tp, tm, te, pot=pot)
     torch.cuda.synchronize()
-    _per_cluster(ens, ens.pos, acc.cpu().numpy(), pot.cpu().numpy(), f"{variant} step 0")
+    _per_cluster(ens, ens.pos, acc.cpu().numpy(), pot.cpu().numpy(), f"{variant} step 0", variant)
     d0 = nbody.step_batched(tp, tv, acc, tm, plan, te, 1.0, 0.0, 1, pot=pot)
     rows = nbody.step_batched(tp, tv, acc, tm, plan, te, 1.0, spec["dt"], spec["steps"], pot=pot)
     torch.cuda.synchronize()
-    _per_cluster(ens, tp.cpu().numpy(), acc.cpu().numpy(), pot.cpu().numpy(), f"{variant} step 100")
+    _per_cluster(ens, tp.cpu().numpy(), acc.cpu().numpy(), pot.cpu().numpy(), f"{variant} step 100",
+                 variant)
     r = dict(rows=rows.cpu().numpy(), e0=float(d0.cpu().numpy()[0, 2]), steps=spec["steps"])
     report_drift("ensemble_512", variant, r)
     plan.close()
