@@ -161,7 +161,7 @@ def tune_batched(variant, c, reps=5, log=None):
     return best, rows
 
 
-def main():
+def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_gfx950.txt"))
     ap.add_argument("--json", default=None)
@@ -175,7 +175,10 @@ def main():
                     help="comma-separated configurations (or jerk shapes) to time (default: all)")
     ap.add_argument("--large-splits", default="1,2",
                     help="grid splits timed for systems of 2^19 particles and more")
-    args = ap.parse_args()
+    ap.add_argument("--batched-classes", default="8,9,10,11,12,13",
+                    help="cluster size classes (log2 N_k) timed for the batched kernel")
+    ap.add_argument("--reps", type=int, default=5, help="timed repetitions per candidate")
+    args = ap.parse_args(argv)
     cfg_list = [int(c) for c in args.configs.split(",")] if args.configs else None
     large = tuple(int(c) for c in args.large_splits.split(","))
     nbody.load()
@@ -190,16 +193,17 @@ def main():
     for variant in args.variants.split(","):
         v = nbody.VARIANTS[variant]
         for c in ([] if args.no_single else range(args.min_log2, args.max_log2 + 1)):
-            (cfg, sp, ms), _ = tune_single(variant, c, log=log, configs=cfg_list, large_splits=large)
+            (cfg, sp, ms), _ = tune_single(variant, c, reps=args.reps, log=log, configs=cfg_list,
+                                           large_splits=large)
             lines.append(f"single {v} {c} {cfg} {sp}")
             print(f"# best {variant} 2^{c}: cfg {cfg} split {sp} {ms:.4f} ms", flush=True)
         for c in ([] if args.no_jerk else range(args.min_log2, args.max_log2 + 1)):
-            (cfg, sp, ms), _ = tune_jerk(variant, c, log=log, shape_list=cfg_list)
+            (cfg, sp, ms), _ = tune_jerk(variant, c, reps=args.reps, log=log, shape_list=cfg_list)
             lines.append(f"jerk {v} {c} {cfg} {sp}")
             print(f"# best jerk {variant} 2^{c}: shape {cfg} split {sp} {ms:.4f} ms", flush=True)
         if not args.no_batched:
-            for c in range(8, 14):
-                (mode, ms), _ = tune_batched(variant, c, log=log)
+            for c in (int(x) for x in args.batched_classes.split(",") if x):
+                (mode, ms), _ = tune_batched(variant, c, reps=args.reps, log=log)
                 lines.append(f"batched {v} {c} {mode}")
                 print(f"# best batched {variant} 2^{c}: mode {mode} {ms:.4f} ms", flush=True)
     with open(args.out, "w") as f:
@@ -208,6 +212,7 @@ def main():
         with open(args.json, "w") as f:
             json.dump(record, f)
     print(f"# wrote {args.out}")
+    return args.out, record
 
 
 if __name__ == "__main__":
