@@ -56,7 +56,9 @@ MEASURED_TRAFFIC = {
     # near/far compensated kernel on half box groups, configuration 25
     ("plummer_256k", "comp", 25, 32): 334628974,
     # near/far with the stored frame, configuration 24
-    ("kroupa_1m", "comp", 24, 8): 7920856990,
+    ("kroupa_1m", "comp", 24, 8): 7896820634,
+    # the plain scalar-stream kernel on the same inputs
+    ("kroupa_1m", "plain", 15, 2): 49393250099,
     # acceleration + jerk kernel (bench.py --hermite): shape 2, split 32
     ("plummer_64k", "plain", "jerk", 2, 32): 98617549,
     # near/far acceleration + jerk kernel on half box groups, shape 12
@@ -571,9 +573,13 @@ def main():
         p_ms, (p_l, p_k) = evaluations(max(3, min(args.steps, 10)), "plain", plain_plan)
         p_avg = p_k / max(p_l, 1)
         p_ach = flops * pairs_per_eval / (p_avg * 1e-3) / 1e12
+        p_traffic = None
+        if plain_plan is None:
+            p_cfg, p_split = nbody.tune_get("plain", n)
+            p_traffic = MEASURED_TRAFFIC.get((name, "plain", p_cfg, p_split))
         plain = {
             "what": "the plain FP32 kernel on the same inputs and GPU, repeated evaluations",
-            "kernel_avg_ms": round(p_avg, 4), "kernel_launches": p_l,
+            "kernel_avg_ms": round(p_avg, 4), "kernel_launches": p_l, "traffic": p_traffic,
             "achieved_TFLOPs": round(p_ach, 2), "frac": round(p_ach / FP32_VECTOR_PEAK_TFLOPS, 4),
             "evaluation_ms_median": round(float(np.median(p_ms)), 4),
             "G_pair_per_s_median": round(pairs_per_eval / (float(np.median(p_ms)) * 1e-3) / 1e9, 1),

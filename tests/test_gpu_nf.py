@@ -57,7 +57,7 @@ def test_configurations_exist_for_compensated_only():
 
 
 @pytest.mark.parametrize("cfg", NF_CFGS)
-@pytest.mark.parametrize("n", [1, 2, 3, 255, 256, 257, 511, 513, 1000, 4099])
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 513, 1000, 4099])
 @pytest.mark.parametrize("eps", [0.01, 0.0])
 def test_sizes_and_splits(cfg, n, eps):
     pos, _, mass = ics.plummer(n, seed=300 + n)
