@@ -160,7 +160,8 @@ nbody_status nbody_step(double *pos, double *vel, double *acc, double *pot,
  * The per-cluster softenings are not part of the plan: every batched call
  * takes them (eps_k), so one plan serves any softenings.
  * Allocates device memory for the work list and a capture stream on the
- * current device. Returns NULL on error (see nbody_last_error). */
+ * current device; the batched calls must be made with that device current
+ * (EINVAL otherwise). Returns NULL on error (see nbody_last_error). */
 nbody_plan *nbody_plan_create(const int64_t *offsets_host, int32_t K,
                               int32_t variant, const char *tune_path);
 
@@ -179,8 +180,9 @@ void nbody_plan_destroy(nbody_plan *plan);
  *   cluster's outputs NaN). G finite. variant must equal the plan's.
  *   ws: ws_bytes >= nbody_workspace_bytes(n_total, K, variant).
  * Errors: EINVAL (NULL plan, NULL eps_k for a non-empty plan, misaligned
- * eps_k, variant differing from the plan's, bad G, NULL or overlapping
- * arrays), ENOTSUP (unknown variant), EWORKSPACE, EHIP. */
+ * eps_k, variant differing from the plan's, a current device other than the
+ * plan's, bad G, NULL or overlapping arrays), ENOTSUP (unknown variant),
+ * EWORKSPACE, EHIP. */
 nbody_status nbody_accel_batched(const double *pos, const double *mass,
                                  const nbody_plan *plan, const double *eps_k,
                                  double G, int32_t variant,

@@ -505,6 +505,10 @@ nbody_status check_batched(const nbody_plan *plan, int32_t variant, const double
   if (plan->n_total > 0 && !eps_k) return fail(NBODY_EINVAL, "eps_k must be non-NULL");
   if (reinterpret_cast<uintptr_t>(eps_k) % alignof(double) != 0)
     return fail(NBODY_EINVAL, "eps_k must be 8-byte aligned");
+  // the plan's device arrays (work list, slot layout) live on one device
+  int dev = -1;
+  if (hipGetDevice(&dev) == hipSuccess && dev != plan->device)
+    return fail(NBODY_EINVAL, "the plan was created on device %d, the current device is %d", plan->device, dev);
   return NBODY_OK;
 }
 
@@ -809,11 +813,10 @@ nbody_status nbody_step_batched(double *pos, double *vel, double *acc, double *p
   hipStream_t s = static_cast<hipStream_t>(stream);
   const WsLayout L = ws_layout(n, variant, plan->K);
   hipError_t e = hipSuccess;
-  if (diag) e = nb::launch_fill_int(at<int>(ws, L.ctr), 1, 0, s);
-  if (e != hipSuccess) return hip_fail(e, "nbody_step_batched");
 
   // Capture one step as a graph (once per argument set), then replay it.
-  // eps_k is read from device memory at every replay.
+  // eps_k is read from device memory at every replay. The capture comes
+  // first, so that a failed capture leaves nothing enqueued on `stream`.
   const void *key[10] = {pos, vel, acc, pot, mass, diag, ws, eps_k, nullptr, nullptr};
   const bool same = plan->exec && std::memcmp(key, plan->key, sizeof(key)) == 0 &&
                     plan->key_g == G && plan->key_dt == dt;
@@ -843,6 +846,7 @@ nbody_status nbody_step_batched(double *pos, double *vel, double *acc, double *p
     plan->key_g = G;
     plan->key_dt = dt;
   }
+  if (diag) e = nb::launch_fill_int(at<int>(ws, L.ctr), 1, 0, s);
   for (int32_t k = 0; k < n_steps && e == hipSuccess; ++k) e = hipGraphLaunch(plan->exec, s);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   return NBODY_OK;
