@@ -335,3 +335,36 @@ def test_noalloc_validates_before_touching_a_device(lib):
         assert "scratch" in lib.nbody_last_error().decode()
         st = lib.nbody_accel_noalloc(far[0], far[1], n, 0.01, 1.0, variant, far[2], None, None)
         assert st in (nbody.OK, nbody.EHIP) and "workspace" not in lib.nbody_last_error().decode()
+
+
+def test_tuning_file_from_the_environment(tmp_path):
+    """NBODY_TUNE names a tuning file read when the table is first used (and
+    again by nbody_tune_reset); a file that does not parse leaves the built-in
+    table. Run in fresh processes, since the table is process-wide."""
+    import subprocess
+    import sys
+
+    good = tmp_path / "t.txt"
+    good.write_text("single 0 20 2 4\njerk 1 18 3 2\n")
+    bad = tmp_path / "b.txt"
+    bad.write_text("single 0 20 999 1\n")
+    code = ("import sys; sys.path.insert(0, %r); from paper_2509_19294_amd import nbody; "
+            "print(nbody.tune_get('plain', 1 << 20), nbody.tune_jerk_get('comp', 1 << 18)); "
+            "nbody.tune_reset(); print(nbody.tune_get('plain', 1 << 20))" % ROOT)
+
+    def run(path):
+        env = dict(os.environ)
+        env.pop("NBODY_TUNE", None)
+        if path is not None:
+            env["NBODY_TUNE"] = str(path)
+        if "NBODY_LIB_UNDER_TEST" in env:
+            env.pop("NBODY_LIB_UNDER_TEST")
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                             timeout=120, cwd=ROOT)
+        assert out.returncode == 0, out.stderr[-2000:]
+        return out.stdout.split("\n")
+
+    default = run(None)
+    lines = run(good)
+    assert lines[0] == "(2, 4) (3, 2)" and lines[1] == "(2, 4)"
+    assert run(bad) == default and default[0] != lines[0]

@@ -66,7 +66,9 @@ def check(got, refs, what=""):
     a, j, p = got
     (ea, ej, ep), (ra, rj, rp) = refs
     e = (orc.rel_rms(a, ra), orc.rel_rms(j, rj), orc.paper_metric(j, ej))
-    print(what, "acc rel-rms", e[0], "jerk rel-rms", e[1], "jerk paper metric (exact inputs)", e[2])
+    print(what, "acc rel-rms", e[0], "jerk rel-rms", e[1], "jerk paper metric (exact inputs)", e[2],
+          "| against the exact inputs: acc rel-rms", orc.rel_rms(a, ea), "jerk rel-rms", orc.rel_rms(j, ej),
+          "acc paper metric", orc.paper_metric(a, ea))
     assert orc.rel_rms(a, ra) <= 1e-5, (what, "acc", orc.rel_rms(a, ra))
     assert orc.max_rel(a, ra) <= 1e-4, (what, "acc max", orc.max_rel(a, ra))
     assert orc.rel_rms(p, rp) <= 1e-5, (what, "pot", orc.rel_rms(p, rp))
