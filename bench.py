@@ -55,10 +55,10 @@ MEASURED_TRAFFIC = {
     ("plummer_64k", "plain", 15, 16): 32541696,
     # near/far compensated kernel on half box groups, configuration 25
     ("plummer_256k", "comp", 25, 32): 334628974,
-    # near/far with the stored frame, configuration 24
-    ("kroupa_1m", "comp", 24, 8): 7896820634,
+    # near/far with the stored frame, configuration 24, per-XCD block order
+    ("kroupa_1m", "comp", 24, 16): 1081401037,
     # the plain scalar-stream kernel on the same inputs
-    ("kroupa_1m", "plain", 15, 2): 49393250099,
+    ("kroupa_1m", "plain", 15, 2): 50237857997,
     # acceleration + jerk kernel (bench.py --hermite): shape 2, split 32
     ("plummer_64k", "plain", "jerk", 2, 32): 98617549,
     # near/far acceleration + jerk kernel on half box groups, shape 12

@@ -58,7 +58,8 @@ WsLayout ws_layout(int64_t n, int32_t variant, int32_t n_clusters = 1, int split
   WsLayout L{};
   const size_t un = static_cast<size_t>(n);
   const size_t jw = variant == NBODY_FP32_COMP ? 2 : 1;
-  const int splits = std::min(nb::max_split(n), std::max(split_cap, 1));
+  // (a batched plan's kernels write their results directly: no split partials)
+  const int splits = n_clusters > 1 ? 0 : std::min(nb::max_split(n), std::max(split_cap, 1));
   size_t off = 0;
   L.packed = off;
   off += align_up(static_cast<size_t>(packed_entries(n, n_clusters)) * jw * sizeof(float4));
@@ -120,10 +121,12 @@ int size_class(int64_t n) {
 // Built-in table, measured on MI355X by paper_2509_19294_amd.autotune
 // (Plummer spheres of 2^c particles, eps = 0.01): {cfg, split} per size class
 // 10..20 for the plain and compensated forms; smaller classes take class 10's
-// entry and larger ones class 20's. Batched modes for classes 8..13.
+// entry and larger ones class 20's (whose compensated split, 16, times equal
+// to 8 and, with the near/far kernel's per-XCD block order, moves about a
+// third of the HBM bytes). Batched modes for classes 8..13.
 const SingleTune kTuned[2][11] = {
     {{5, 4}, {5, 8}, {5, 8}, {4, 8}, {15, 16}, {15, 16}, {15, 16}, {13, 16}, {13, 32}, {13, 8}, {15, 2}},
-    {{5, 4}, {5, 8}, {4, 4}, {0, 16}, {15, 16}, {15, 32}, {15, 32}, {25, 32}, {25, 32}, {25, 8}, {24, 8}},
+    {{5, 4}, {5, 8}, {4, 4}, {0, 16}, {15, 16}, {15, 32}, {15, 32}, {25, 32}, {25, 32}, {25, 8}, {24, 16}},
 };
 const int kTunedBatched[2][6] = {{8, 4, 4, 4, 4, 4}, {1, 4, 4, 4, 4, 4}};
 // Acceleration + jerk kernel: {shape, split} per size class 10..20, measured
@@ -237,8 +240,8 @@ SingleTune jerk_tune(int32_t variant, int64_t n) {
   SingleTune t = g_jerk[variant][size_class(n)];
   if (g_jerk_forced[variant] >= 0) t = SingleTune{g_jerk_forced[variant] % 1000, g_jerk_forced[variant] / 1000};
   if (t.split <= 0) t.split = nb::jerk_default_split(n, t.cfg);
-  // the partial buffer holds at most kPartCap entries
-  while (t.split > 1 && static_cast<int64_t>(t.split) * n > nb::kPartCap) t.split /= 2;
+  // the partial buffer holds at most kJerkPartCap entries
+  while (t.split > 1 && static_cast<int64_t>(t.split) * n > nb::kJerkPartCap) t.split /= 2;
   return t;
 }
 

@@ -44,6 +44,30 @@ struct OutArgs {
 // removed again in FP64. The expression matches the in-loop one bit for bit.
 __device__ __forceinline__ float self_term(float m, float eps2f) { return m * rsq(eps2f); }
 
+// Target block and grid split of a block launched on a one-dimensional grid
+// of nblk x split blocks. Blocks go to the 8 XCDs in turn (block L to XCD
+// L % 8), each XCD with its own L2. order 0 takes the splits one after
+// another (block L = split * nblk + target block); order 1 (split a multiple
+// of 8) gives XCD x the splits x, x + 8, ...; order 2 (8 a multiple of split,
+// nblk * split a multiple of 8) gives XCD x split x % split only. With 1 and
+// 2 the blocks an XCD runs at a time stage the same split's sources, which
+// then stay in that XCD's L2 instead of every XCD streaming every split.
+__device__ __forceinline__ void xcd_block(uint32_t L, uint32_t nblk, uint32_t split, int order,
+                                          uint32_t &bx, uint32_t &by) {
+  if (order == 1) {
+    const uint32_t x = L & 7u, r = L >> 3;
+    by = x + 8u * (r / nblk);
+    bx = r % nblk;
+  } else if (order == 2) {
+    const uint32_t x = L & 7u, r = L >> 3;
+    by = x % split;
+    bx = r * (8u / split) + x / split;
+  } else {
+    by = L / nblk;
+    bx = L % nblk;
+  }
+}
+
 // Four consecutive float4 words, 64-byte aligned: one scalar load.
 struct alignas(64) Quad {
   float4 v[4];

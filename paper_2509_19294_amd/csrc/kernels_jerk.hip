@@ -498,7 +498,7 @@ int jerk_default_split(int64_t n, int cfg) {
   const int64_t blocks = (n + ib - 1) / ib;
   int split = 1;
   while (split < kMaxSplit && blocks * split < 8192 && n / (split * 2) >= 1024 &&
-         static_cast<int64_t>(split * 2) * n <= kPartCap)
+         static_cast<int64_t>(split * 2) * n <= kJerkPartCap)
     split *= 2;
   return split;
 }
@@ -517,7 +517,7 @@ hipError_t launch_pair_jerk(int cfg, bool comp, const float4 *packed, const doub
                             double *pot, float4 *part, hipStream_t stream, hipEvent_t after_pair) {
   if (n <= 0) return hipSuccess;
   const int ib = jerk_targets_per_block(cfg);
-  if (ib == 0 || split > kMaxSplit || (split > 1 && static_cast<int64_t>(split) * n > kPartCap))
+  if (ib == 0 || split > kMaxSplit || (split > 1 && static_cast<int64_t>(split) * n > kJerkPartCap))
     return hipErrorInvalidValue;
   const int64_t nblk = (n + ib - 1) / ib;
   if (split < 1) split = 1;

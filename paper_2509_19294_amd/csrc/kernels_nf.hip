@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(nf_waves<FR
 pair_nf_kernel(const double *__restrict__ spos, const double *__restrict__ smass,
                const double *__restrict__ box, const double *__restrict__ bfr,
                const double *__restrict__ hbox, int64_t n, float eps2f, int64_t split_len,
-               NfOut o) {
+               uint32_t nblk, uint32_t nsplit, int order, NfOut o) {
   constexpr int NG = 4 / SW;          // target groups of 64 lanes per block
   constexpr int IB = NG * 64 * K;
   constexpr int kHalf = kNfTile / 2;
@@ -76,9 +76,11 @@ pair_nf_kernel(const double *__restrict__ spos, const double *__restrict__ smass
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const int wj = wave % SW, wg = wave / SW;
-  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * IB;
+  uint32_t bx, by;
+  xcd_block(blockIdx.x, nblk, nsplit, order, bx, by);
+  const int64_t i0 = static_cast<int64_t>(bx) * IB;
   const int64_t i1 = i0 + IB < n ? i0 + IB : n;
-  const int64_t J0 = static_cast<int64_t>(blockIdx.y) * split_len;
+  const int64_t J0 = static_cast<int64_t>(by) * split_len;
   const int64_t J1 = J0 + split_len < n ? J0 + split_len : n;
 
   // the block's box: union of its groups' boxes (or its half group's box);
@@ -308,7 +310,7 @@ pair_nf_kernel(const double *__restrict__ spos, const double *__restrict__ smass
     const int64_t i = iidx[k];
     if (i >= i1) continue;
     if (o.part) {
-      float4 *P = o.part + (static_cast<int64_t>(blockIdx.y) * o.n + i) * 2;
+      float4 *P = o.part + (static_cast<int64_t>(by) * o.n + i) * 2;
       store_stream(P, make_float4(ah[k][0], ah[k][1], ah[k][2], ah[k][3]));
       store_stream(P + 1, make_float4(al[k][0], al[k][1], al[k][2], al[k][3]));
     } else {
@@ -357,14 +359,23 @@ __global__ __launch_bounds__(256) void combine_nf_kernel(const float4 *__restric
 }
 
 template <int K, int SW, int FR = 0>
-hipError_t launch_nf_t(bool eps0, dim3 grid, const OrderWs &w, int64_t n, float eps2f,
-                       int64_t split_len, const NfOut &o, hipStream_t st) {
+hipError_t launch_nf_t(bool eps0, uint32_t nblk, uint32_t split, const OrderWs &w, int64_t n,
+                       float eps2f, int64_t split_len, const NfOut &o, hipStream_t st) {
+  // Block order across the XCDs (xcd_block). A split's sources are staged
+  // from 32 B of FP64 position and mass each; once a split holds more than
+  // a quarter of an XCD's 4 MB L2, per-XCD splits keep them there (else each
+  // XCD's L2 cycles through every split). Below that the plain order is
+  // better: it lets each XCD read only its share of the targets per split.
+  const uint64_t total = static_cast<uint64_t>(nblk) * split;
+  const bool big = static_cast<uint64_t>(n / split) * 32 > (uint64_t{1} << 20);
+  const int order = !big ? 0 : (split % 8 == 0 ? 1 : (8 % split == 0 && total % 8 == 0 ? 2 : 0));
+  const dim3 grid(static_cast<unsigned>(total));
   if (eps0)
-    pair_nf_kernel<K, SW, FR, true>
-        <<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, w.bfr, w.hbox, n, eps2f, split_len, o);
+    pair_nf_kernel<K, SW, FR, true><<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, w.bfr, w.hbox, n,
+                                                          eps2f, split_len, nblk, split, order, o);
   else
-    pair_nf_kernel<K, SW, FR, false>
-        <<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, w.bfr, w.hbox, n, eps2f, split_len, o);
+    pair_nf_kernel<K, SW, FR, false><<<grid, 256, 0, st>>>(w.spos, w.smass, w.box, w.bfr, w.hbox, n,
+                                                           eps2f, split_len, nblk, split, order, o);
   return hipGetLastError();
 }
 
@@ -392,18 +403,18 @@ hipError_t launch_pair_nf(int k, int sw, int fr, const OrderWs &w, int64_t n, do
     o.acc = acc;
     o.pot = pot;
   }
-  dim3 grid(static_cast<unsigned>(nblk), static_cast<unsigned>(split));
+  const uint32_t nb = static_cast<uint32_t>(nblk), sp = static_cast<uint32_t>(split);
   hipError_t e;
   if (fr == 1 && k == 2 && sw == 2)
-    e = launch_nf_t<2, 2, 1>(eps0, grid, w, n, eps2f, split_len, o, stream);
+    e = launch_nf_t<2, 2, 1>(eps0, nb, sp, w, n, eps2f, split_len, o, stream);
   else if (fr == 2 && k == 2 && sw == 4)
-    e = launch_nf_t<2, 4, 2>(eps0, grid, w, n, eps2f, split_len, o, stream);
+    e = launch_nf_t<2, 4, 2>(eps0, nb, sp, w, n, eps2f, split_len, o, stream);
   else if (fr != 0) return hipErrorInvalidValue;
-  else if (k == 2 && sw == 1) e = launch_nf_t<2, 1>(eps0, grid, w, n, eps2f, split_len, o, stream);
-  else if (k == 4 && sw == 1) e = launch_nf_t<4, 1>(eps0, grid, w, n, eps2f, split_len, o, stream);
-  else if (k == 4 && sw == 4) e = launch_nf_t<4, 4>(eps0, grid, w, n, eps2f, split_len, o, stream);
-  else if (k == 4 && sw == 2) e = launch_nf_t<4, 2>(eps0, grid, w, n, eps2f, split_len, o, stream);
-  else if (k == 2 && sw == 2) e = launch_nf_t<2, 2>(eps0, grid, w, n, eps2f, split_len, o, stream);
+  else if (k == 2 && sw == 1) e = launch_nf_t<2, 1>(eps0, nb, sp, w, n, eps2f, split_len, o, stream);
+  else if (k == 4 && sw == 1) e = launch_nf_t<4, 1>(eps0, nb, sp, w, n, eps2f, split_len, o, stream);
+  else if (k == 4 && sw == 4) e = launch_nf_t<4, 4>(eps0, nb, sp, w, n, eps2f, split_len, o, stream);
+  else if (k == 4 && sw == 2) e = launch_nf_t<4, 2>(eps0, nb, sp, w, n, eps2f, split_len, o, stream);
+  else if (k == 2 && sw == 2) e = launch_nf_t<2, 2>(eps0, nb, sp, w, n, eps2f, split_len, o, stream);
   else return hipErrorInvalidValue;
   if (e == hipSuccess && after_pair) e = hipEventRecord(after_pair, stream);
   if (e != hipSuccess || split == 1) return e;

@@ -405,7 +405,7 @@ hipError_t launch_pair_nf_jerk(int k, int sw, const OrderWs &w, const double *sv
                                double *pot, float4 *part, hipStream_t stream, hipEvent_t after_pair) {
   if (n <= 0) return hipSuccess;
   if (split < 1) split = 1;
-  if (split > kMaxSplit || (split > 1 && static_cast<int64_t>(split) * n > kPartCap))
+  if (split > kMaxSplit || (split > 1 && static_cast<int64_t>(split) * n > kJerkPartCap))
     return hipErrorInvalidValue;
   int64_t split_len = (n + split - 1) / split;
   split_len = (split_len + kNfjTile - 1) / kNfjTile * kNfjTile;

@@ -10,7 +10,8 @@ namespace nb {
 
 constexpr int kDiagLen = 16;
 constexpr int kMaxSplit = 32;         // largest grid-level j-split
-constexpr int64_t kPartCap = int64_t{1} << 23;  // most split partial entries kept
+constexpr int64_t kPartCap = int64_t{1} << 24;  // most split partial entries kept (force)
+constexpr int64_t kJerkPartCap = int64_t{1} << 23;  // the same for acceleration + jerk
 constexpr int kPad = 64;              // packed arrays are padded to a multiple of this
 constexpr int kDiagBlocks = 512;      // blocks of the first diagnostics pass
 constexpr int kDiagThreads = 256;
