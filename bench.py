@@ -39,6 +39,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_CLOCK_MHZ = 2400.0           # the clock that peak is quoted at
 FLOPS_PER_INTERACTION = 20        # the conventional count for one softened pair
 # Acceleration + jerk: the force's 20 plus the jerk's own FP32 work per pair
 # (relative velocity 3, d.w 5, alpha 2, w - alpha d 6, accumulation 6; an FMA
@@ -99,7 +100,7 @@ def full_run(name, variant, steps=None):
 
     from oracle import cpu as ocpu
     from oracle import oracle as orc
-    from paper_2509_19294_amd import ics, nbody
+    from paper_2509_19294_amd import energy, ics, nbody
 
     nbody.load()
     dev = torch.device("cuda:0")
@@ -435,7 +436,7 @@ def main():
 
     import torch
 
-    from paper_2509_19294_amd import ics, nbody
+    from paper_2509_19294_amd import energy, ics, nbody
 
     nbody.load()
     dev = torch.device("cuda:0")
@@ -506,6 +507,10 @@ def main():
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream(dev)
+    # the graphics clock, sampled over the timed steps and the repeated force
+    # evaluations (the fraction of peak is also stated at that clock)
+    clock = energy.ClockSampler(0)
+    clock.__enter__()
     # one event between consecutive steps: the first and last bracket the
     # timed region, the others give per-step durations (median, min)
     marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
@@ -543,6 +548,8 @@ def main():
         return times, kern
 
     force_ms, kern_eval = evaluations(max(args.steps, 5), on_plan=plan)
+    clock.__exit__(None, None, None)
+    clk = clock.result()
     if plan is not None:
         # The batched force kernel runs inside the graph replay: its duration
         # comes from the same kernels launched eagerly on the same stream.
@@ -630,7 +637,13 @@ def main():
             "kernel_avg_ms": round(kernel_avg_ms, 4),
             "kernel_launches": launches,
             "flops_per_interaction": flops,
+            # the same fraction against the peak scaled to the sampled clock
+            "frac_at_measured_clock": (round(achieved / (FP32_VECTOR_PEAK_TFLOPS * clk["gfx_mhz_median"]
+                                                         / PEAK_CLOCK_MHZ), 4)
+                                       if clk["gfx_mhz_median"] else None),
         },
+        "clock": {"what": "graphics clock sampled every 50 ms over the timed steps and the repeated "
+                          "force evaluations (mean over the XCDs)", **clk},
     }
     if plain is not None:
         out["plain_same_inputs"] = plain

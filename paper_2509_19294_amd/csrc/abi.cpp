@@ -261,6 +261,7 @@ struct Timing {
   size_t used = 0;               // events recorded since the last read
 };
 Timing g_timing;
+std::mutex g_timing_mu;  // guards g_timing (launches may come from several host threads)
 
 bool capturing(hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -280,6 +281,7 @@ hipEvent_t timing_event() {
 // Records the start event; returns the stop event to record after the launch
 // (nullptr when timing is off or the stream is being captured).
 hipEvent_t timing_begin(hipStream_t st) {
+  std::lock_guard<std::mutex> g(g_timing_mu);
   if (!g_timing.on || capturing(st)) return nullptr;
   hipEvent_t a = timing_event();
   if (!a) return nullptr;
@@ -998,6 +1000,7 @@ nbody_status nbody_tune_load(const char *path) {
 
 nbody_status nbody_timing_enable(int32_t on) {
   g_err.clear();
+  std::lock_guard<std::mutex> g(g_timing_mu);
   g_timing.on = on != 0;
   g_timing.used = 0;
   return NBODY_OK;
@@ -1006,6 +1009,7 @@ nbody_status nbody_timing_enable(int32_t on) {
 nbody_status nbody_timing_read(int64_t *launches, double *total_ms) {
   g_err.clear();
   if (!launches || !total_ms) return fail(NBODY_EINVAL, "launches and total_ms must be non-NULL");
+  std::lock_guard<std::mutex> g(g_timing_mu);
   double sum = 0.0;
   int64_t count = 0;
   for (size_t k = 0; k + 1 < g_timing.used; k += 2) {

@@ -114,6 +114,84 @@ def temperatures(device_index: int = 0) -> dict:
     return out
 
 
+def _number(v):
+    """A positive reading as float, or None ("N/A" strings, zeros, sentinels)."""
+    return float(v) if isinstance(v, (int, float)) and 0 < v < 65535 else None
+
+
+def gfx_clock_mhz(smi, handle):
+    """The graphics clock in MHz: the mean over the XCDs' current clocks
+    from the GPU metrics table, else the clock query's current value; None
+    when neither can be read."""
+    try:
+        m = smi.amdsmi_get_gpu_metrics_info(handle)
+        per_xcd = [x for x in (_number(v) for v in (m.get("current_gfxclks") or [])) if x]
+        if per_xcd:
+            return sum(per_xcd) / len(per_xcd)
+        v = _number(m.get("current_gfxclk"))
+        if v:
+            return v
+    except Exception:
+        pass
+    try:
+        return _number(smi.amdsmi_get_clock_info(handle, smi.AmdSmiClkType.GFX).get("clk"))
+    except Exception:
+        return None
+
+
+class ClockSampler:
+    """Context manager sampling the GPU's graphics clock in a background
+    thread over its body (default every 50 ms), for stating a throughput
+    against the peak at the clock the GPU actually ran at."""
+
+    def __init__(self, device_index: int = 0, interval_s: float = 0.05):
+        self.device_index = device_index
+        self.interval_s = interval_s
+        self.notes: list[str] = []
+        self.samples: list[float] = []
+        self._smi = self._handle = self._thread = None
+        self._stop = threading.Event()
+
+    def _run(self):
+        while not self._stop.is_set():
+            v = gfx_clock_mhz(self._smi, self._handle)
+            if v is not None:
+                self.samples.append(v)
+            self._stop.wait(self.interval_s)
+
+    def __enter__(self):
+        self._smi, self._handle, notes = _open_handle(self.device_index)
+        self.notes.extend(notes)
+        if self._handle is not None:
+            self._thread = threading.Thread(target=self._run, daemon=True)
+            self._thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        self._stop.set()
+        if self._thread is not None:
+            self._thread.join()
+        if self._smi is not None:
+            try:
+                self._smi.amdsmi_shut_down()
+            except Exception:
+                pass
+        return False
+
+    def result(self) -> dict:
+        """Median, min and max of the samples (MHz), None without samples."""
+        xs = sorted(self.samples)
+        if not xs:
+            if not self.notes:
+                self.notes.append("no clock sample over the region")
+            return {"gfx_mhz_median": None, "gfx_mhz_min": None, "gfx_mhz_max": None,
+                    "samples": 0, "notes": self.notes}
+        k = len(xs)
+        med = xs[k // 2] if k % 2 else 0.5 * (xs[k // 2 - 1] + xs[k // 2])
+        return {"gfx_mhz_median": round(med, 1), "gfx_mhz_min": round(xs[0], 1),
+                "gfx_mhz_max": round(xs[-1], 1), "samples": k, "notes": self.notes}
+
+
 class EnergyMeter:
     """Context manager measuring GPU and host energy over its body."""
 

@@ -52,5 +52,13 @@ def test_bench_json_line(extra):
     rl = line["roofline"]
     assert rl["bound"] == "alu" and rl["unit"] == "TFLOP/s" and rl["peak"] == 157.3
     assert np.isclose(rl["frac"], rl["achieved"] / rl["peak"], atol=1e-4)
+    ck = line["clock"]
+    print("clock", ck, "frac", rl["frac"], "at measured clock", rl["frac_at_measured_clock"], flush=True)
+    if ck["gfx_mhz_median"] is not None:
+        assert 300 < ck["gfx_mhz_median"] < 3000 and ck["samples"] > 0
+        assert np.isclose(rl["frac_at_measured_clock"],
+                          rl["achieved"] / (rl["peak"] * ck["gfx_mhz_median"] / 2400.0), atol=1e-3)
+    else:
+        assert rl["frac_at_measured_clock"] is None and ck["notes"]
     cb = line["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0

@@ -54,3 +54,43 @@ def test_counter_that_did_not_advance_is_none():
     assert r["gpu_energy_j"] is None and r["gpu_mean_power_w"] is None
     assert any("did not advance" in n for n in r["notes"])
 
+
+
+def test_clock_sampler_without_gpu_reports_none(monkeypatch):
+    monkeypatch.setattr(energy, "_amdsmi", lambda: (None, "amdsmi not importable: test"))
+    with energy.ClockSampler(interval_s=0.01) as cs:
+        pass
+    r = cs.result()
+    assert r["gfx_mhz_median"] is None and r["samples"] == 0 and r["notes"]
+
+
+def test_clock_reading_prefers_the_per_xcd_clocks():
+    class Smi:
+        class AmdSmiClkType:
+            GFX = 0
+
+        def __init__(self, metrics, clk):
+            self.metrics, self.clk = metrics, clk
+
+        def amdsmi_get_gpu_metrics_info(self, h):
+            if self.metrics is None:
+                raise RuntimeError("no metrics table")
+            return self.metrics
+
+        def amdsmi_get_clock_info(self, h, t):
+            return {"clk": self.clk}
+
+    # invalid entries ("N/A", the 0xffff sentinel, 0) are left out of the mean
+    per_xcd = {"current_gfxclks": [2400, 2380, "N/A", 65535, 0, 2390, 2410, 2420], "current_gfxclk": 2000}
+    assert abs(energy.gfx_clock_mhz(Smi(per_xcd, 1500), None) - 2400.0) < 1e-9
+    assert energy.gfx_clock_mhz(Smi({"current_gfxclks": [], "current_gfxclk": 2100}, 1500), None) == 2100.0
+    assert energy.gfx_clock_mhz(Smi(None, 1500), None) == 1500.0
+    assert energy.gfx_clock_mhz(Smi(None, "N/A"), None) is None
+
+
+def test_clock_sampler_statistics():
+    cs = energy.ClockSampler()
+    cs.samples = [2400.0, 2100.0, 2380.0, 2390.0]
+    r = cs.result()
+    assert r["gfx_mhz_median"] == 2385.0 and r["gfx_mhz_min"] == 2100.0 and r["gfx_mhz_max"] == 2400.0
+    assert r["samples"] == 4
