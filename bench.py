@@ -55,7 +55,7 @@ DEFAULT_VARIANT = {"plummer_1k": "plain", "plummer_64k": "plain", "plummer_256k"
 MEASURED_TRAFFIC = {
     ("plummer_64k", "plain", 15, 16): 32541696,
     # near/far compensated kernel on half box groups, configuration 25
-    ("plummer_256k", "comp", 25, 32): 334628974,
+    ("plummer_256k", "comp", 25, 32): 334614642,
     # near/far with the stored frame, configuration 24, per-XCD block order
     ("kroupa_1m", "comp", 24, 16): 1081401037,
     # the plain scalar-stream kernel on the same inputs
