@@ -500,3 +500,42 @@ def test_batched_graph_steps(variant):
     np.testing.assert_allclose(d_gpu[-1, 0], k_tot, rtol=1e-8)
     np.testing.assert_allclose(d_gpu[-1, 12], len(ens.sizes), rtol=1e-13)
     plan.close()
+
+
+@pytest.mark.parametrize("variant", ["comp", "plain"])
+def test_batched_graph_replays_match_eager_steps(variant):
+    """Each replay of the plan's captured step against the same step done
+    eagerly (kick and drift as torch FP64 operations, forces from an eager
+    batched launch), with other eager launches on the same workspace and
+    host synchronisations between the replays: every replay rebuilds what
+    the graph reads (packed slots, work counters), so none inherits a
+    previous launch's state."""
+    ens = _small_ensemble(k=10, seed=21)
+    dt, h = 1.0 / 256, 0.5 / 256
+    plan = nbody.Plan(ens.offsets, variant)
+    te = T(ens.eps)
+    tm = T(ens.mass)
+    x, v = T(ens.pos), T(ens.vel)
+    a, _ = plan.accel(x, tm, te)
+    xr, vr, ar = x.clone(), v.clone(), a.clone()
+    other = T(ens.pos[::-1].copy())
+    diag = torch.empty((1, nbody.DIAG_LEN), dtype=torch.float64, device=DEV)
+    for step in range(6):
+        nbody.step_batched(x, v, a, tm, plan, te, 1.0, dt, 1, diag=diag)
+        torch.cuda.synchronize()
+        # the same step, eagerly
+        vr = vr + h * ar
+        xr = xr + dt * vr
+        ar, pr = plan.accel(xr, tm, te)
+        vr = vr + h * ar
+        # unrelated eager work on the shared workspace between replays
+        plan.accel(other, tm, te)
+        torch.cuda.synchronize()
+        for got, ref, name in ((x, xr, "pos"), (v, vr, "vel"), (a, ar, "acc")):
+            g, r = got.cpu().numpy(), ref.cpu().numpy()
+            scale = np.abs(r).max()
+            assert np.abs(g - r).max() <= 1e-12 * scale, (variant, step, name, np.abs(g - r).max() / scale)
+        kin = 0.5 * float((tm * (vr * vr).sum(1)).sum())
+        np.testing.assert_allclose(diag[0, nbody.DIAG["K"]].item(), kin, rtol=1e-12)
+        np.testing.assert_allclose(diag[0, nbody.DIAG["W"]].item(), 0.5 * float((tm * pr).sum()), rtol=1e-10)
+    plan.close()
