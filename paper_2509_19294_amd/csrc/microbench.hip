@@ -25,6 +25,16 @@
 //     sources' mass-weighted coordinates times r^-3, and masses times r^-1)
 //     in place of the 3 fma + 1 add into the accumulators; sources differ
 //     per lane, as that lane layout needs
+//  14-19 operand placement and co-issue (mb_asm_kernel): sixteen
+//     independent accumulations per lane written in inline asm with fixed
+//     registers (a VGPR's bank is its index mod 4; every case uses v0-v71, so
+//     occupancy is the same):
+//     14 v_fmac_f32 acc, a, b with acc, a, b in three different banks
+//     15 the same with acc, a, b all in bank 0
+//     16 v_fmac_f32 acc, s, b: an SGPR operand in every instruction
+//     17 one instruction in four with an SGPR operand, the rest as 14
+//     18 v_sub_f32 acc, s, acc: an SGPR operand in every instruction (VOP2)
+//     19 two v_rsq_f32 (chains of their own) among sixteen v_fmac_f32 as in 14
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -211,9 +221,59 @@ __global__ __launch_bounds__(1024) void mb_kernel(float *out, int iters, float s
   out[static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x] = s;
 }
 
+// Operand-placement cases (14-19): ALU-only asm loops, 16 instructions per
+// iteration (18 for case 19), on fixed registers v0-v71 and s90-s91.
+#define MB_F3(d) "v_fmac_f32_e32 " d ", v65, v70\n"   // banks: d (0), 1, 2
+#define MB_F1(d) "v_fmac_f32_e32 " d ", v64, v68\n"   // banks: d (0), 0, 0
+#define MB_FS(d) "v_fmac_f32_e32 " d ", s91, v65\n"   // an SGPR operand
+#define MB_SS(d) "v_sub_f32_e32 " d ", s91, " d "\n"   // VOP2 with an SGPR
+#define MB_RQ(d) "v_rsq_f32_e32 " d ", " d "\n"
+#define MB_16(F) F("v0") F("v4") F("v8") F("v12") F("v16") F("v20") F("v24") F("v28") \
+  F("v32") F("v36") F("v40") F("v44") F("v48") F("v52") F("v56") F("v60")
+#define MB_INIT(F) F("v0") F("v4") F("v8") F("v12") F("v16") F("v20") F("v24") F("v28") \
+  F("v32") F("v36") F("v40") F("v44") F("v48") F("v52") F("v56") F("v60")
+#define MB_ONE(d) "v_mov_b32 " d ", 1.0\n"
+#define MB_LOOP(BODY)                                                                         \
+  asm volatile(MB_INIT(MB_ONE) "v_mov_b32 v1, 2.0\n v_mov_b32 v37, 2.0\n"                    \
+               "v_mov_b32 v64, 0.5\n v_mov_b32 v65, 0.5\n"                                   \
+               "v_mov_b32 v68, 0.25\n v_mov_b32 v70, 0.25\n s_mov_b32 s91, 0.5\n"            \
+               "s_mov_b32 s90, %1\n"                                                          \
+               "1:\n" BODY "s_sub_u32 s90, s90, 1\n s_cmp_lg_u32 s90, 0\n s_cbranch_scc1 1b\n" \
+               "v_mov_b32 %0, v0\n"                                                           \
+               : "=v"(r)                                                                     \
+               : "s"(iters)                                                                  \
+               : "s90", "s91", "scc", "v0", "v1", "v2", "v3", "v4", "v5", "v6", "v7", "v8",  \
+                 "v9", "v10", "v11", "v12", "v13", "v14", "v15", "v16", "v17", "v18", "v19",   \
+                 "v20", "v21", "v22", "v23", "v24", "v25", "v26", "v27", "v28", "v29", "v30",  \
+                 "v31", "v32", "v33", "v34", "v35", "v36", "v37", "v38", "v39", "v40", "v41",  \
+                 "v42", "v43", "v44", "v45", "v46", "v47", "v48", "v49", "v50", "v51", "v52",  \
+                 "v53", "v54", "v55", "v56", "v57", "v58", "v59", "v60", "v61", "v62", "v63",  \
+                 "v64", "v65", "v66", "v67", "v68", "v69", "v70", "v71")
+
+template <int OP>
+__global__ __launch_bounds__(256) void mb_asm_kernel(float *out, int iters) {
+  float r = 0.f;
+  if constexpr (OP == 14) MB_LOOP(MB_16(MB_F3));
+  if constexpr (OP == 15) MB_LOOP(MB_16(MB_F1));
+  if constexpr (OP == 16) MB_LOOP(MB_16(MB_FS));
+  if constexpr (OP == 17)
+    MB_LOOP(MB_FS("v0") MB_F3("v4") MB_F3("v8") MB_F3("v12") MB_FS("v16") MB_F3("v20")
+                MB_F3("v24") MB_F3("v28") MB_FS("v32") MB_F3("v36") MB_F3("v40") MB_F3("v44")
+                    MB_FS("v48") MB_F3("v52") MB_F3("v56") MB_F3("v60"));
+  if constexpr (OP == 18) MB_LOOP(MB_16(MB_SS));
+  if constexpr (OP == 19)   // the two rsq chains (v1, v37) feed no accumulation
+    MB_LOOP(MB_RQ("v1") MB_F3("v0") MB_F3("v4") MB_F3("v8") MB_F3("v12") MB_F3("v16")
+                MB_F3("v20") MB_F3("v24") MB_F3("v28") MB_RQ("v37") MB_F3("v32") MB_F3("v36")
+                    MB_F3("v40") MB_F3("v44") MB_F3("v48") MB_F3("v52") MB_F3("v56") MB_F3("v60"));
+  out[static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x] = r;
+}
+
 template <int OP, int ILP>
 hipError_t launch(float *out, int blocks, int threads, int iters) {
-  mb_kernel<OP, ILP><<<blocks, threads, 0, nullptr>>>(out, iters, 1.0f);
+  if constexpr (OP >= 14)
+    mb_asm_kernel<OP><<<blocks, threads, 0, nullptr>>>(out, iters);
+  else
+    mb_kernel<OP, ILP><<<blocks, threads, 0, nullptr>>>(out, iters, 1.0f);
   return hipGetLastError();
 }
 
@@ -233,7 +293,13 @@ hipError_t launch_op(int op, float *out, int blocks, int threads, int iters) {
     case 10: return launch<10, ILP>(out, blocks, threads, iters);
     case 11: return launch<11, ILP>(out, blocks, threads, iters);
     case 12: return launch<12, ILP>(out, blocks, threads, iters);
-    default: return launch<13, ILP>(out, blocks, threads, iters);
+    case 13: return launch<13, ILP>(out, blocks, threads, iters);
+    case 14: return launch<14, ILP>(out, blocks, threads, iters);
+    case 15: return launch<15, ILP>(out, blocks, threads, iters);
+    case 16: return launch<16, ILP>(out, blocks, threads, iters);
+    case 17: return launch<17, ILP>(out, blocks, threads, iters);
+    case 18: return launch<18, ILP>(out, blocks, threads, iters);
+    default: return launch<19, ILP>(out, blocks, threads, iters);
   }
 }
 
@@ -241,14 +307,15 @@ hipError_t launch_op(int op, float *out, int blocks, int threads, int iters) {
 
 extern "C" {
 
-// Runs operation `op` with `ilp` chains per lane (1, 2, 4, 8 or 16) on
+// Runs operation `op` with `ilp` chains per lane (1, 2, 4, 8 or 16; the asm
+// cases 14-19 always run 16 and take 256 threads) on
 // `blocks` x `threads` (threads a multiple of 64, at most 1024) for `iters`
 // iterations; returns the median duration in ms of `reps` timed launches
 // after one warm-up. out: device buffer of blocks * threads floats.
 // Returns 0 on success, -1 on bad arguments, else the HIP error code.
 int mb_run(int op, int ilp, float *out, int blocks, int threads, int iters, int reps,
            double *ms_out) {
-  if (op < 0 || op > 13 || reps < 1 || reps > 64 || !out || !ms_out || blocks < 1 ||
+  if (op < 0 || op > 19 || (op >= 14 && threads != 256) || reps < 1 || reps > 64 || !out || !ms_out || blocks < 1 ||
       threads < 64 || threads > 1024 || threads % 64 != 0 || iters < 1)
     return -1;
   if (ilp != 1 && ilp != 2 && ilp != 4 && ilp != 8 && ilp != 16) return -1;

@@ -1,6 +1,6 @@
 """Instruction-rate microbenchmarks on gfx950 (the pair kernel's budget).
 
-    python -m paper_2509_19294_amd.microbench
+    python -m paper_2509_19294_amd.microbench [--no-build]
 
 Builds ``libnbody_micro.so`` from ``csrc/microbench.hip`` with the main
 library's compiler flags and prints one JSON object. For each case: the
@@ -38,6 +38,13 @@ OPS = {
     11: ("lds_bcast+4fma_f32", 5),
     12: ("sym_rot_pair_arith", 16 * 19),   # per chain-iteration: 16 pair evaluations
     13: ("pair_arith_mfma_accum", 11),     # 8 VALU + rsq + 2 MFMA per interaction
+    # operand placement (inline asm, 16 chains, fixed registers; ilp is 16)
+    14: ("fmac_vgpr_three_banks", 1),
+    15: ("fmac_vgpr_one_bank", 1),
+    16: ("fmac_sgpr_every_instr", 1),
+    17: ("fmac_sgpr_one_in_four", 1),
+    18: ("sub_sgpr_every_instr", 1),
+    19: ("rsq_one_in_nine_fmac", 18 / 16),
 }
 
 # (op, ilp, blocks, threads)
@@ -53,12 +60,14 @@ CASES = [
     (11, 8, 4096, 256),
     (12, 2, 4096, 256), (12, 4, 4096, 256), (12, 8, 4096, 256), (12, 4, 1024, 256),
     (13, 1, 4096, 256), (13, 2, 4096, 256), (13, 4, 4096, 256), (13, 8, 4096, 256),
+    (14, 16, 4096, 256), (15, 16, 4096, 256), (16, 16, 4096, 256), (17, 16, 4096, 256),
+    (18, 16, 4096, 256), (19, 16, 4096, 256),
 ]
 
 
 def build() -> str:
     tmp = LIB + ".tmp"
-    cmd = [nbuild.hipcc(), *nbuild.HIPCC_FLAGS, SRC, "-o", tmp]
+    cmd = [nbuild.hipcc(), *nbuild.HIPCC_FLAGS, "-shared", SRC, "-o", tmp]
     subprocess.run(cmd, check=True, capture_output=True)
     os.replace(tmp, LIB)
     return LIB
@@ -104,5 +113,8 @@ def run(reps: int = 5, clock_ghz: float = 2.4, target: float = 3e10):
 
 
 if __name__ == "__main__":
-    build()
+    import sys
+
+    if "--no-build" not in sys.argv[1:]:   # the library built in-tree beforehand
+        build()
     print(json.dumps(run()))
