@@ -35,6 +35,7 @@
 //     17 one instruction in four with an SGPR operand, the rest as 14
 //     18 v_sub_f32 acc, s, acc: an SGPR operand in every instruction (VOP2)
 //     19 two v_rsq_f32 (chains of their own) among sixteen v_fmac_f32 as in 14
+//     20 four softened pairs per iteration with hand-placed registers
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -235,6 +236,11 @@ __global__ __launch_bounds__(1024) void mb_kernel(float *out, int iters, float s
 #define MB_ONE(d) "v_mov_b32 " d ", 1.0\n"
 #define MB_LOOP(BODY)                                                                         \
   asm volatile(MB_INIT(MB_ONE) "v_mov_b32 v1, 2.0\n v_mov_b32 v37, 2.0\n"                    \
+               "v_mov_b32 v41, 0.25\n v_mov_b32 v42, -0.5\n v_mov_b32 v43, 0.5\n"               \
+               "v_mov_b32 v45, -0.25\n v_mov_b32 v46, 0.5\n v_mov_b32 v47, 0.5\n"               \
+               "v_mov_b32 v49, 0.5\n v_mov_b32 v50, -1.0\n v_mov_b32 v53, -1.0\n"               \
+               "v_mov_b32 v54, 0.5\n v_mov_b32 v57, 0\n v_mov_b32 v58, 0\n v_mov_b32 v59, 0\n" \
+               "v_mov_b32 v61, 0\n v_mov_b32 v62, 0\n v_mov_b32 v63, 0\n"                      \
                "v_mov_b32 v64, 0.5\n v_mov_b32 v65, 0.5\n"                                   \
                "v_mov_b32 v68, 0.25\n v_mov_b32 v70, 0.25\n s_mov_b32 s91, 0.5\n"            \
                "s_mov_b32 s90, %1\n"                                                          \
@@ -249,6 +255,73 @@ __global__ __launch_bounds__(1024) void mb_kernel(float *out, int iters, float s
                  "v42", "v43", "v44", "v45", "v46", "v47", "v48", "v49", "v50", "v51", "v52",  \
                  "v53", "v54", "v55", "v56", "v57", "v58", "v59", "v60", "v61", "v62", "v63",  \
                  "v64", "v65", "v66", "v67", "v68", "v69", "v70", "v71")
+
+// Case 20: four softened pairs (two register-resident sources, two targets,
+// the two targets' instruction streams interleaved) with every temporary
+// placed by hand: separations in banks 0-2, r^-3 m in bank 3, so no
+// instruction reads three operands from one bank; sources v40-v47, targets
+// v48-v54, accumulators v56-v63, softening^2 in s91.
+#define MB_PAIR4 \
+  "v_sub_f32_e32 v0, v40, v48\n" \
+  "v_sub_f32_e32 v8, v40, v52\n" \
+  "v_sub_f32_e32 v1, v41, v49\n" \
+  "v_sub_f32_e32 v9, v41, v53\n" \
+  "v_sub_f32_e32 v2, v42, v50\n" \
+  "v_sub_f32_e32 v10, v42, v54\n" \
+  "v_fma_f32 v4, v0, v0, s91\n" \
+  "v_fma_f32 v12, v8, v8, s91\n" \
+  "v_fmac_f32_e32 v4, v1, v1\n" \
+  "v_fmac_f32_e32 v12, v9, v9\n" \
+  "v_fmac_f32_e32 v4, v2, v2\n" \
+  "v_fmac_f32_e32 v12, v10, v10\n" \
+  "v_rsq_f32_e32 v4, v4\n" \
+  "v_rsq_f32_e32 v12, v12\n" \
+  "s_nop 0\n" \
+  "s_nop 0\n" \
+  "v_mul_f32_e32 v5, v43, v4\n" \
+  "v_mul_f32_e32 v13, v43, v12\n" \
+  "v_mul_f32_e32 v6, v4, v4\n" \
+  "v_mul_f32_e32 v14, v12, v12\n" \
+  "v_mul_f32_e32 v3, v5, v6\n" \
+  "v_mul_f32_e32 v11, v13, v14\n" \
+  "v_fmac_f32_e32 v56, v3, v0\n" \
+  "v_fmac_f32_e32 v60, v11, v8\n" \
+  "v_fmac_f32_e32 v57, v3, v1\n" \
+  "v_fmac_f32_e32 v61, v11, v9\n" \
+  "v_fmac_f32_e32 v58, v3, v2\n" \
+  "v_fmac_f32_e32 v62, v11, v10\n" \
+  "v_add_f32_e32 v59, v59, v5\n" \
+  "v_add_f32_e32 v63, v63, v13\n" \
+  "v_sub_f32_e32 v0, v44, v48\n" \
+  "v_sub_f32_e32 v8, v44, v52\n" \
+  "v_sub_f32_e32 v1, v45, v49\n" \
+  "v_sub_f32_e32 v9, v45, v53\n" \
+  "v_sub_f32_e32 v2, v46, v50\n" \
+  "v_sub_f32_e32 v10, v46, v54\n" \
+  "v_fma_f32 v4, v0, v0, s91\n" \
+  "v_fma_f32 v12, v8, v8, s91\n" \
+  "v_fmac_f32_e32 v4, v1, v1\n" \
+  "v_fmac_f32_e32 v12, v9, v9\n" \
+  "v_fmac_f32_e32 v4, v2, v2\n" \
+  "v_fmac_f32_e32 v12, v10, v10\n" \
+  "v_rsq_f32_e32 v4, v4\n" \
+  "v_rsq_f32_e32 v12, v12\n" \
+  "s_nop 0\n" \
+  "s_nop 0\n" \
+  "v_mul_f32_e32 v5, v47, v4\n" \
+  "v_mul_f32_e32 v13, v47, v12\n" \
+  "v_mul_f32_e32 v6, v4, v4\n" \
+  "v_mul_f32_e32 v14, v12, v12\n" \
+  "v_mul_f32_e32 v3, v5, v6\n" \
+  "v_mul_f32_e32 v11, v13, v14\n" \
+  "v_fmac_f32_e32 v56, v3, v0\n" \
+  "v_fmac_f32_e32 v60, v11, v8\n" \
+  "v_fmac_f32_e32 v57, v3, v1\n" \
+  "v_fmac_f32_e32 v61, v11, v9\n" \
+  "v_fmac_f32_e32 v58, v3, v2\n" \
+  "v_fmac_f32_e32 v62, v11, v10\n" \
+  "v_add_f32_e32 v59, v59, v5\n" \
+  "v_add_f32_e32 v63, v63, v13\n"
 
 template <int OP>
 __global__ __launch_bounds__(256) void mb_asm_kernel(float *out, int iters) {
@@ -265,6 +338,8 @@ __global__ __launch_bounds__(256) void mb_asm_kernel(float *out, int iters) {
     MB_LOOP(MB_RQ("v1") MB_F3("v0") MB_F3("v4") MB_F3("v8") MB_F3("v12") MB_F3("v16")
                 MB_F3("v20") MB_F3("v24") MB_F3("v28") MB_RQ("v37") MB_F3("v32") MB_F3("v36")
                     MB_F3("v40") MB_F3("v44") MB_F3("v48") MB_F3("v52") MB_F3("v56") MB_F3("v60"));
+  if constexpr (OP == 20)
+    MB_LOOP(MB_PAIR4);
   out[static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x] = r;
 }
 
@@ -299,7 +374,8 @@ hipError_t launch_op(int op, float *out, int blocks, int threads, int iters) {
     case 16: return launch<16, ILP>(out, blocks, threads, iters);
     case 17: return launch<17, ILP>(out, blocks, threads, iters);
     case 18: return launch<18, ILP>(out, blocks, threads, iters);
-    default: return launch<19, ILP>(out, blocks, threads, iters);
+    case 19: return launch<19, ILP>(out, blocks, threads, iters);
+    default: return launch<20, ILP>(out, blocks, threads, iters);
   }
 }
 
@@ -308,14 +384,14 @@ hipError_t launch_op(int op, float *out, int blocks, int threads, int iters) {
 extern "C" {
 
 // Runs operation `op` with `ilp` chains per lane (1, 2, 4, 8 or 16; the asm
-// cases 14-19 always run 16 and take 256 threads) on
+// cases 14-20 always run 16 and take 256 threads) on
 // `blocks` x `threads` (threads a multiple of 64, at most 1024) for `iters`
 // iterations; returns the median duration in ms of `reps` timed launches
 // after one warm-up. out: device buffer of blocks * threads floats.
 // Returns 0 on success, -1 on bad arguments, else the HIP error code.
 int mb_run(int op, int ilp, float *out, int blocks, int threads, int iters, int reps,
            double *ms_out) {
-  if (op < 0 || op > 19 || (op >= 14 && threads != 256) || reps < 1 || reps > 64 || !out || !ms_out || blocks < 1 ||
+  if (op < 0 || op > 20 || (op >= 14 && threads != 256) || reps < 1 || reps > 64 || !out || !ms_out || blocks < 1 ||
       threads < 64 || threads > 1024 || threads % 64 != 0 || iters < 1)
     return -1;
   if (ilp != 1 && ilp != 2 && ilp != 4 && ilp != 8 && ilp != 16) return -1;

@@ -45,6 +45,7 @@ OPS = {
     17: ("fmac_sgpr_one_in_four", 1),
     18: ("sub_sgpr_every_instr", 1),
     19: ("rsq_one_in_nine_fmac", 18 / 16),
+    20: ("pair_arith_asm_banked", 56 / 16),   # 4 pairs (14 VALU each) per iteration
 }
 
 # (op, ilp, blocks, threads)
@@ -61,7 +62,7 @@ CASES = [
     (12, 2, 4096, 256), (12, 4, 4096, 256), (12, 8, 4096, 256), (12, 4, 1024, 256),
     (13, 1, 4096, 256), (13, 2, 4096, 256), (13, 4, 4096, 256), (13, 8, 4096, 256),
     (14, 16, 4096, 256), (15, 16, 4096, 256), (16, 16, 4096, 256), (17, 16, 4096, 256),
-    (18, 16, 4096, 256), (19, 16, 4096, 256),
+    (18, 16, 4096, 256), (19, 16, 4096, 256), (20, 16, 4096, 256),
 ]
 
 
@@ -101,11 +102,13 @@ def run(reps: int = 5, clock_ghz: float = 2.4, target: float = 3e10):
         row = {"op": name, "ilp": ilp, "blocks": blocks, "threads": threads,
                "waves_per_simd": round(waves_per_simd, 2), "ms": round(ms.value, 4),
                "lane_instr_per_cu_clk": round(rate / (cus * clock_ghz * 1e9), 2)}
-        if op in (10, 12, 13):
+        if op in (10, 12, 13, 20):
             # each symmetric evaluation serves two interactions
             per_eval = 2 if op == 12 else 1
             evals = 16 if op == 12 else 1
             inter = float(blocks) * threads * iters * ilp * evals * per_eval / (ms.value * 1e-3)
+            if op == 20:   # four pairs per iteration (ilp counts its 16 instruction slots)
+                inter = float(blocks) * threads * iters * 4 / (ms.value * 1e-3)
             row["G_interactions_per_s"] = round(inter / 1e9, 1)
             row["pct_fp32_peak_at_20_flops"] = round(100 * 20 * inter / 157.3e12, 1)
         rows.append(row)
