@@ -224,3 +224,102 @@ def test_random_systems_acceleration_and_jerk(seed, n, shift, bulk, eps_rel, G, 
     assert np.all(np.isfinite(j)), what
     _note("jerk", ej, sj)
     assert np.all(ej <= C * U * sj + 1e-300), (what, "jerk", float(np.max(ej / np.maximum(sj, 1e-300))))
+
+
+def _vec_err(x, ref):
+    return np.linalg.norm(x - ref, axis=1)
+
+
+@settings(max_examples=40, **SETTINGS)
+@given(seed=st.integers(0, 2 ** 31 - 1), n=st.integers(2, 200), eps_rel=st.sampled_from([1e-3, 0.05, 0.5]),
+       G=st.floats(0.5, 2.0), dt=st.sampled_from([1.0 / 64, 1.0 / 256, 1.0 / 1024]),
+       variant=st.sampled_from(["plain", "comp"]), cfg_pick=st.integers(0, 10 ** 6),
+       split=st.sampled_from([1, 3, 8]))
+def test_random_kdk_steps_from_the_gpu_state(seed, n, eps_rel, G, dt, variant, cfg_pick, split):
+    """Three KDK steps, one call each, under a forced random configuration.
+    Each step is checked from the state the GPU itself held before it: the
+    drift is the FP64 update of that state, the new accelerations meet the
+    force bound, and the closing kick differs from the oracle's only by
+    dt/2 times that force error."""
+    pos, mass = system(seed, n, 1.0, 0.0, 1.0, 0.1)
+    rng = np.random.default_rng(seed + 7)
+    vel = rng.normal(0.0, 0.3, (n, 3))
+    eps = eps_rel
+    cls = int(math.floor(math.log2(n)))
+    tp, tv, tm = T(pos), T(vel), T(mass)
+    nbody.tune_set(variant, cls, cfg_pick % len(nbody.tune_configs(variant)), split)
+    try:
+        acc, _ = nbody.accel(tp, tm, eps, G, variant)
+        for step in range(3):
+            x0, v0, a0 = tp.cpu().numpy(), tv.cpu().numpy(), acc.cpu().numpy()
+            diag = nbody.step(tp, tv, acc, tm, eps, G, dt, 1, variant)
+            torch.cuda.synchronize()
+            x1, v1, a1 = tp.cpu().numpy(), tv.cpu().numpy(), acc.cpu().numpy()
+            vh = v0 + 0.5 * dt * a0
+            xr = x0 + dt * vh
+            scale_x = np.abs(xr).max() + 1e-300
+            assert np.abs(x1 - xr).max() <= 1e-14 * scale_x, (step, "drift")
+            rp, rm = (rounded(x1, mass) if variant == "plain" else (x1, mass))
+            ra, rpot = orc.accel_pot(rp, rm, eps, G)
+            sa, sp = pair_sums(rp, rm, eps, G)
+            ea = _vec_err(a1, ra)
+            _note("kdk acc", ea, sa)
+            assert np.all(ea <= C * U * sa + 1e-300), (step, variant, "acc")
+            ev = _vec_err(v1, vh + 0.5 * dt * ra)
+            assert np.all(ev <= 0.5 * dt * C * U * sa + 1e-14 * (np.abs(vh).max() + 1e-300)), (step, "kick")
+            k = 0.5 * float(np.sum(mass * np.einsum("ik,ik->i", v1, v1)))
+            np.testing.assert_allclose(diag[0, nbody.DIAG["K"]].item(), k, rtol=1e-12)
+    finally:
+        nbody.tune_set(variant, cls, -1)
+
+
+@settings(max_examples=30, **SETTINGS)
+@given(seed=st.integers(0, 2 ** 31 - 1), n=st.integers(2, 200), eps_rel=st.sampled_from([1e-3, 0.05, 0.5]),
+       G=st.floats(0.5, 2.0), dt=st.sampled_from([1.0 / 64, 1.0 / 256, 1.0 / 1024]),
+       variant=st.sampled_from(["plain", "comp"]), shape_pick=st.integers(0, 10 ** 6),
+       split=st.sampled_from([0, 1, 8]))
+def test_random_hermite_steps_from_the_gpu_state(seed, n, eps_rel, G, dt, variant, shape_pick, split):
+    """Two Hermite steps, one call each, under a forced random acceleration
+    + jerk shape. From the GPU's own state before each step: the predicted
+    state is the FP64 predictor; the corrector's result differs from the one
+    built on the oracle's acceleration and jerk at that predicted state by at
+    most what the force and jerk bounds carry through the corrector."""
+    pos, mass = system(seed, n, 1.0, 0.0, 1.0, 0.1)
+    rng = np.random.default_rng(seed + 11)
+    vel = rng.normal(0.0, 0.3, (n, 3))
+    eps = eps_rel
+    tp, tv, tm = T(pos), T(vel), T(mass)
+    nbody.tune_jerk_set(variant, shape_pick % len(nbody.jerk_shapes(variant)), split)
+    try:
+        acc, jerk, _ = nbody.accel_jerk(tp, tv, tm, eps, G, variant)
+        for step in range(2):
+            x0, v0 = tp.cpu().numpy(), tv.cpu().numpy()
+            a0, j0 = acc.cpu().numpy(), jerk.cpu().numpy()
+            nbody.step_hermite(tp, tv, acc, jerk, tm, eps, G, dt, 1, variant)
+            torch.cuda.synchronize()
+            x1, v1 = tp.cpu().numpy(), tv.cpu().numpy()
+            a1, j1 = acc.cpu().numpy(), jerk.cpu().numpy()
+            xp = x0 + dt * v0 + (dt * dt / 2.0) * a0 + (dt ** 3 / 6.0) * j0
+            vp = v0 + dt * a0 + (dt * dt / 2.0) * j0
+            rp, rm = (rounded(xp, mass) if variant == "plain" else (xp, mass))
+            ra, rj, _ = orc.accel_jerk(rp, vp, rm, eps, G)
+            spread = 2.0 * float(np.max(np.linalg.norm(vp - vp.mean(0), axis=1)))
+            sa, sp, sj = pair_sums(rp, rm, eps, G, vel=vp, vspread=spread)
+            # position rounding of the plain form moves the predicted state by
+            # u |x| per coordinate, which the oracle on rounded inputs absorbs
+            da, dj = C * U * sa, C * U * sj
+            ea, ej = _vec_err(a1, ra), _vec_err(j1, rj)
+            _note("hermite acc", ea, sa)
+            _note("hermite jerk", ej, sj)
+            assert np.all(ea <= da + 1e-300), (step, variant, "acc")
+            assert np.all(ej <= dj + 1e-300), (step, variant, "jerk")
+            vr = v0 + (dt / 2.0) * (a0 + ra) + (dt * dt / 12.0) * (j0 - rj)
+            xr = x0 + (dt / 2.0) * (v0 + vr) + (dt * dt / 12.0) * (a0 - ra)
+            dv = (dt / 2.0) * da + (dt * dt / 12.0) * dj
+            dx = (dt / 2.0) * dv + (dt * dt / 12.0) * da
+            fv = 1e-14 * (np.abs(vr).max() + 1e-300)
+            fx = 1e-14 * (np.abs(xr).max() + 1e-300)
+            assert np.all(_vec_err(v1, vr) <= dv + fv), (step, "corrector v")
+            assert np.all(_vec_err(x1, xr) <= dx + fx), (step, "corrector x")
+    finally:
+        nbody.tune_jerk_set(variant, -1)
